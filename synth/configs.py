@@ -1,0 +1,112 @@
+"""Workload constants: the five synthetic series and the frozen solver settings.
+
+Every value the paper leaves open is fixed here once, so that the oracle and the
+GPU library run with identical settings:
+
+* the energy is the plain sum of squared differences plus lambda times the sum
+  of squared forward differences of both displacement components (no 1/2);
+* lambda = 0.1 for every series;
+* the gradient-descent step tau is fixed once for all series (see ``TAU``);
+* the stopping rule is the relative energy decrease, checked per pyramid level.
+
+The series themselves stand in for the transmission-electron-microscopy data of
+the paper's evaluation (Section 5), which is not available: a Gaussian
+atom-column lattice with per-frame drift, a smooth sinusoidal distortion and
+Gaussian noise.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field, replace
+
+# Gradient-descent step.  The paper gives a multilevel gradient-flow minimiser
+# (Section 2.3.1) but no step size.  On the 256x256 series the energy decreases
+# monotonically up to the stopping step for tau up to at least 1.0; 0.5 keeps a
+# factor-2 margin and converges in roughly 60-190 iterations per level, so the
+# iteration counts stay uneven (the load imbalance the scan has to absorb).
+TAU = 0.5
+LAMBDA = 0.1
+BASE_SEED = 1410
+
+
+@dataclass(frozen=True)
+class SolverParams:
+    levels: int = 1          # pyramid levels, level 0 = full resolution
+    max_iter: int = 200      # per level
+    fixed_iter: bool = False  # True: exactly max_iter updates per level
+    tau: float = TAU
+    lam: float = LAMBDA
+    rel_tol: float = 1e-5    # stop when E_{t-1} - E_t <= rel_tol * E_{t-1}
+
+
+@dataclass(frozen=True)
+class SeriesSpec:
+    n_frames: int
+    height: int
+    width: int
+    spacing: float = 8.0      # lattice spacing a [px]
+    sigma: float = 1.5        # atom-column Gaussian width [px]
+    drift: float = 2.0        # bound D of the drift trajectory [px]
+    distort: float = 0.5      # sinusoidal distortion amplitude A_d [px]
+    noise: float = 0.05       # noise sigma
+    extra_noise_frac: float = 0.0  # fraction of frames with extra noise
+    extra_noise: float = 0.0       # extra noise sigma on those frames
+    seed: int = BASE_SEED
+
+
+@dataclass(frozen=True)
+class Config:
+    index: int
+    name: str
+    series: SeriesSpec
+    solver: SolverParams
+    algo: str = "seq"        # scan plan used by the series registration
+    chunk: int = 0           # chunk length for the hierarchical plan
+    global_algo: str = "lf"  # global phase of the hierarchical plan
+    pairs: int = 0           # differentiation workload: number of frame pairs
+    extras: dict = field(default_factory=dict)
+
+
+CONFIGS: dict[int, Config] = {
+    1: Config(1, "series16-64x64-seq",
+              SeriesSpec(16, 64, 64, spacing=8.0, drift=2.0, distort=0.5,
+                         noise=0.05, seed=BASE_SEED + 1),
+              SolverParams(levels=1, max_iter=50, fixed_iter=True),
+              algo="seq"),
+    2: Config(2, "series256-256x256-hier",
+              SeriesSpec(256, 256, 256, spacing=8.0, drift=4.0, distort=0.5,
+                         noise=0.1, seed=BASE_SEED + 2),
+              SolverParams(levels=2, max_iter=200),
+              algo="hier", chunk=16, global_algo="lf"),
+    3: Config(3, "series1024-512x512-hier",
+              SeriesSpec(1024, 512, 512, spacing=8.0, drift=8.0, distort=1.5,
+                         noise=0.1, extra_noise_frac=0.1, extra_noise=0.3,
+                         seed=BASE_SEED + 3),
+              SolverParams(levels=3, max_iter=200),
+              algo="hier", chunk=32, global_algo="lf"),
+    4: Config(4, "pairs64-512x512-autograd",
+              SeriesSpec(65, 512, 512, spacing=8.0, drift=8.0, distort=1.5,
+                         noise=0.1, extra_noise_frac=0.1, extra_noise=0.3,
+                         seed=BASE_SEED + 4),
+              SolverParams(levels=1),
+              pairs=64),
+    5: Config(5, "series4096-1024x1024-hier",
+              SeriesSpec(4096, 1024, 1024, spacing=12.0, drift=16.0,
+                         distort=2.0, noise=0.1, seed=BASE_SEED + 5),
+              SolverParams(levels=4, max_iter=200),
+              algo="hier", chunk=64, global_algo="lf"),
+}
+
+
+def get_config(index: int, **overrides) -> Config:
+    """Return config ``index``; keyword overrides replace series fields
+    (``n_frames``, ``height``, ...) or solver fields (``levels``, ...)."""
+    cfg = CONFIGS[index]
+    s_keys = {k: v for k, v in overrides.items() if k in SeriesSpec.__dataclass_fields__}
+    p_keys = {k: v for k, v in overrides.items() if k in SolverParams.__dataclass_fields__}
+    c_keys = {k: v for k, v in overrides.items()
+              if k in ("algo", "chunk", "global_algo", "pairs")}
+    rest = set(overrides) - set(s_keys) - set(p_keys) - set(c_keys)
+    if rest:
+        raise KeyError(f"unknown override(s): {sorted(rest)}")
+    return replace(cfg, series=replace(cfg.series, **s_keys),
+                   solver=replace(cfg.solver, **p_keys), **c_keys)

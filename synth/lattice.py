@@ -1,0 +1,128 @@
+"""Synthetic atom-column lattice series with known deformations.
+
+Stand-in for the paper's high-resolution TEM series (Section 5, aluminium
+oxidation data, not available here).  Recipe, per frame k of a series:
+
+* lattice  L(q) = sum over the 3x3 nearest lattice sites s of
+  exp(-|q - o - s|^2 / (2 sigma^2)), square lattice of spacing a, random
+  origin o ~ U[0, a)^2, amplitude 1 on a zero background;
+* frame    f_k(x) = L(x - d_k - w_k(x)) + n_k(x), n_k iid N(0, noise^2),
+  plus N(0, extra_noise^2) on a seeded subset of frames;
+* drift    d_0 = 0, d_k = d_{k-1} + U[-delta, delta]^2 reflected into
+  [-D, D], delta = min(a/4, D/2), so consecutive frames stay within half a
+  lattice period of each other (Section 2.3.2) while the series as a whole
+  drifts further;
+* distortion w_k(x) = A_d (sin(2 pi y / H + th_k1), sin(2 pi x / W + th_k2)),
+  th_0 ~ U[0, 2 pi)^2 and th_k = th_{k-1} + U[-0.25, 0.25]^2.
+
+Ground truth: the displacement u_ik with f_k(x + u_ik(x)) ~ f_i(x) is p - x
+where p solves p - d_k - w_k(p) = x - d_i - w_i(x) (a contraction, solved by
+fixed-point iteration).
+
+Scalar per-frame parameters come from NumPy's PCG64 seeded with the series
+seed; pixel fields are evaluated with torch in float64 on the requested device
+(noise from a torch generator seeded the same way), then rounded to float32.
+A series generated on the CPU and one generated on a GPU therefore share
+drift, distortion and origin but not the noise; every consumer is given the
+same generated frames.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from .configs import SeriesSpec
+
+
+@dataclass
+class Series:
+    spec: SeriesSpec
+    frames: torch.Tensor      # [N][H][W] float32
+    drift: np.ndarray         # [N][2]  (x, y) in px
+    theta: np.ndarray         # [N][2]
+    origin: np.ndarray        # [2]
+    noisy: np.ndarray         # indices of frames with extra noise
+
+
+def _frame_params(spec: SeriesSpec):
+    rng = np.random.Generator(np.random.PCG64(spec.seed))
+    n = spec.n_frames
+    a, dmax = spec.spacing, spec.drift
+    delta = min(a / 4.0, dmax / 2.0)
+    origin = rng.uniform(0.0, a, size=2)
+    drift = np.zeros((n, 2))
+    for k in range(1, n):
+        v = drift[k - 1] + rng.uniform(-delta, delta, size=2)
+        v = np.where(v > dmax, 2 * dmax - v, v)
+        v = np.where(v < -dmax, -2 * dmax - v, v)
+        drift[k] = v
+    theta = np.zeros((n, 2))
+    theta[0] = rng.uniform(0.0, 2 * math.pi, size=2)
+    for k in range(1, n):
+        theta[k] = theta[k - 1] + rng.uniform(-0.25, 0.25, size=2)
+    n_extra = int(math.floor(spec.extra_noise_frac * n))
+    noisy = np.sort(rng.choice(n, size=n_extra, replace=False)) if n_extra else np.zeros(0, np.int64)
+    return origin, drift, theta, noisy
+
+
+def _distortion(spec: SeriesSpec, theta, qx, qy):
+    wx = spec.distort * torch.sin(2 * math.pi * qy / spec.height + float(theta[0]))
+    wy = spec.distort * torch.sin(2 * math.pi * qx / spec.width + float(theta[1]))
+    return wx, wy
+
+
+def lattice_image(spec: SeriesSpec, origin, qx: torch.Tensor, qy: torch.Tensor) -> torch.Tensor:
+    """Evaluate the lattice L at sample positions (qx, qy) (float64 tensors)."""
+    a, s2 = spec.spacing, 2.0 * spec.sigma ** 2
+    rx = qx - float(origin[0])
+    ry = qy - float(origin[1])
+    mx = torch.round(rx / a)
+    my = torch.round(ry / a)
+    out = torch.zeros_like(qx)
+    for di in (-1.0, 0.0, 1.0):
+        ex = rx - (mx + di) * a
+        for dj in (-1.0, 0.0, 1.0):
+            ey = ry - (my + dj) * a
+            out += torch.exp(-(ex * ex + ey * ey) / s2)
+    return out
+
+
+def make_series(spec: SeriesSpec, device="cpu", frames_dtype=torch.float32) -> Series:
+    """Generate the frame series of ``spec`` on ``device``."""
+    origin, drift, theta, noisy = _frame_params(spec)
+    dev = torch.device(device)
+    H, W, N = spec.height, spec.width, spec.n_frames
+    yy, xx = torch.meshgrid(torch.arange(H, dtype=torch.float64, device=dev),
+                            torch.arange(W, dtype=torch.float64, device=dev), indexing="ij")
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(spec.seed)
+    frames = torch.empty((N, H, W), dtype=frames_dtype, device=dev)
+    noisy_set = set(int(i) for i in noisy)
+    for k in range(N):
+        wx, wy = _distortion(spec, theta[k], xx, yy)
+        f = lattice_image(spec, origin, xx - drift[k, 0] - wx, yy - drift[k, 1] - wy)
+        if spec.noise > 0:
+            f += spec.noise * torch.randn((H, W), generator=gen, dtype=torch.float64, device=dev)
+        if k in noisy_set and spec.extra_noise > 0:
+            f += spec.extra_noise * torch.randn((H, W), generator=gen, dtype=torch.float64, device=dev)
+        frames[k] = f.to(frames_dtype)
+    return Series(spec, frames, drift, theta, origin, noisy)
+
+
+def ground_truth(series: Series, i: int, k: int, iters: int = 60) -> np.ndarray:
+    """Analytic displacement u_ik as a float64 array [2][H][W] (x, y planes)."""
+    spec = series.spec
+    H, W = spec.height, spec.width
+    yy, xx = torch.meshgrid(torch.arange(H, dtype=torch.float64),
+                            torch.arange(W, dtype=torch.float64), indexing="ij")
+    wix, wiy = _distortion(spec, series.theta[i], xx, yy)
+    cx = xx - series.drift[i, 0] - wix + series.drift[k, 0]
+    cy = yy - series.drift[i, 1] - wiy + series.drift[k, 1]
+    px, py = cx.clone(), cy.clone()
+    for _ in range(iters):
+        wkx, wky = _distortion(spec, series.theta[k], px, py)
+        px, py = cx + wkx, cy + wky
+    return torch.stack([px - xx, py - yy]).numpy()

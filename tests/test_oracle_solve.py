@@ -1,0 +1,156 @@
+"""Pins of the oracle's gradient descent, multilevel solve and scan executor:
+identity registration, brute-force shift search, recovery of known synthetic
+deformations (proposed acceptance thresholds, the paper prints none)."""
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+from oracle import registration as reg
+from oracle.scan import run_scan
+from synth import SeriesSpec, get_config, ground_truth, lattice_image, make_series
+from synth.configs import SolverParams
+
+import torch
+
+
+def _lattice_pair(shift, size=24, spacing=8.0):
+    spec = SeriesSpec(2, size, size, spacing=spacing, noise=0.0)
+    origin = np.array([3.3, 2.1])
+    yy, xx = torch.meshgrid(torch.arange(size, dtype=torch.float64),
+                            torch.arange(size, dtype=torch.float64), indexing="ij")
+    R = lattice_image(spec, origin, xx, yy).numpy()
+    T = lattice_image(spec, origin, xx - shift[0], yy - shift[1]).numpy()
+    return R, T          # T(x + shift) = R(x)
+
+
+# ----------------------------------------------------------------- T3
+
+@pytest.mark.parametrize("levels", [1, 2, 3])
+def test_identity_registration_of_identical_frames(levels):
+    cfg = get_config(1, n_frames=2, height=32, width=48)
+    f = make_series(cfg.series).frames[0].numpy().astype(np.float64)
+    pyr = reg.pyramid(f, levels)
+    res = reg.register(pyr, pyr, None, SolverParams(levels=levels, max_iter=30))
+    assert np.all(res.u == 0.0)
+    # zero residual and zero gradient: the relative rule stops at t = 1
+    assert res.iters == [1] * levels
+
+
+def test_fixed_iterations_are_exact():
+    R, T = _lattice_pair((0.4, -0.3))
+    res = reg.solve_level(R, T, np.zeros((2, 24, 24)), 0.5, 0.1, 7, True, 1e-5)
+    assert res.iters == 7 and len(res.energies) == 7
+
+
+def test_stopping_rule_special_cases():
+    R, T = _lattice_pair((0.6, 0.2))
+    u0 = np.zeros((2, 24, 24))
+    # a huge tolerance stops at the first check
+    assert reg.solve_level(R, T, u0, 0.5, 0.1, 50, False, 1e9).iters == 1
+    # tolerance 0 runs until the energy no longer decreases
+    res = reg.solve_level(R, T, u0, 0.5, 0.1, 2000, False, 0.0)
+    e = res.energies
+    assert res.iters < 2000
+    assert all(e[t] < e[t - 1] for t in range(1, len(e) - 1))
+    assert e[-1] >= e[-2]
+
+
+def test_nonfinite_energy_stops():
+    R, T = _lattice_pair((0.5, 0.5))
+    R = R.copy()
+    R[3, 3] = np.nan
+    res = reg.solve_level(R, T, np.zeros((2, 24, 24)), 0.5, 0.1, 20, False, 1e-5)
+    assert res.status == reg.STATUS_NONFINITE and res.iters == 0
+
+
+# ----------------------------------------------------------------- T4
+
+def _exhaustive_shift(R, T, lam=0.1):
+    """argmin of E over constant shifts on a 1/64 px grid in [-3, 3]^2."""
+    def E(s):
+        u = np.empty((2,) + R.shape)
+        u[0], u[1] = s
+        return reg.energy(R, T, u, lam)
+    coarse = np.arange(-3, 3 + 1e-9, 1 / 8)
+    best = min(((E((sx, sy)), sx, sy) for sx in coarse for sy in coarse))
+    fine = np.arange(-8, 9) / 64
+    best = min(((E((best[1] + dx, best[2] + dy)), best[1] + dx, best[2] + dy)
+                for dx in fine for dy in fine))
+    return np.array(best[1:])
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_brute_force_shift_search(seed):
+    s_true = np.random.default_rng(100 + seed).uniform(-1.5, 1.5, size=2)
+    R, T = _lattice_pair(s_true)
+    s_star = _exhaustive_shift(R, T)
+    assert np.all(np.abs(s_star - s_true) < 0.1)
+
+    # (i) gradient descent restricted to constant fields lands on s*
+    v = np.zeros(2)
+    for _ in range(3000):
+        u = np.empty((2, 24, 24))
+        u[0], u[1] = v
+        _, g = reg.energy_and_gradient(R, T, u, 0.1)
+        v = v - 0.004 * g.reshape(2, -1).sum(axis=1)
+    assert np.all(np.abs(v - s_star) <= 1 / 64 + 1e-12)
+
+    # (ii) a stiff regulariser keeps the dense field near-constant at s*
+    p = SolverParams(levels=1, max_iter=20000, tau=0.05, lam=2.0, rel_tol=1e-12)
+    res = reg.register([R], [T], None, p)
+    assert np.all(np.abs(res.u[:, 4:-4, 4:-4].reshape(2, -1).mean(axis=1) - s_star) < 0.02)
+
+    # (iii) the default operator from the identity stays in s*'s basin
+    # (shift below half a lattice period, Section 2.3.2)
+    res = reg.register([R], [T], None, SolverParams(levels=1, max_iter=500))
+    assert np.all(np.abs(res.u[:, 4:-4, 4:-4].reshape(2, -1).mean(axis=1) - s_star) < 0.1)
+
+
+# ----------------------------------------------------------------- T5
+
+def _atom_mask(series, clean_spec, i):
+    clean = make_series(clean_spec).frames[i].numpy()
+    b = int(series.spec.drift + 2)
+    m = np.zeros(clean.shape, bool)
+    m[b:-b, b:-b] = True
+    return m & (clean >= np.exp(-2.0))   # within ~2 sigma of an atom centre
+
+
+@pytest.mark.parametrize("levels", [1, 2])
+def test_recovery_of_synthetic_deformation_noise_free(levels):
+    cfg = get_config(1, n_frames=6, noise=0.0, levels=levels, max_iter=500, fixed_iter=False)
+    S = make_series(cfg.series)
+    fr = S.frames.numpy().astype(np.float64)
+    res = run_scan(fr, cfg.solver, "seq")
+    mask = _atom_mask(S, cfg.series, 0)
+    for k in (1, 3, 5):
+        e = np.abs(res.phi0[k - 1] - ground_truth(S, 0, k))[:, mask]
+        assert e.max() <= 0.1 and np.sqrt((e ** 2).mean()) <= 0.03, k
+    assert np.all(np.abs(S.drift[1:] - S.drift[:-1]) < cfg.series.spacing / 2)
+
+
+def test_recovery_of_synthetic_deformation_noisy():
+    cfg = get_config(1, n_frames=4, noise=0.05, levels=1, max_iter=500, fixed_iter=False)
+    S = make_series(cfg.series)
+    res = run_scan(S.frames.numpy().astype(np.float64), cfg.solver, "seq")
+    mask = _atom_mask(S, replace(cfg.series, noise=0.0), 0)
+    for k in (1, 3):
+        e = np.abs(res.phi0[k - 1] - ground_truth(S, 0, k))[:, mask]
+        assert np.sqrt((e ** 2).mean()) <= 0.12
+
+
+def test_scan_plans_agree_with_sequential_recursion_on_clean_series():
+    # Associativity in practice (Section 2.3.3): tree orders land on the same
+    # deformation as the sequential recursion up to the solver's accuracy.
+    cfg = get_config(1, n_frames=9, noise=0.0, levels=1, max_iter=300, fixed_iter=False)
+    S = make_series(cfg.series)
+    fr = S.frames.numpy().astype(np.float64)
+    seq = run_scan(fr, cfg.solver, "seq")
+    mask = _atom_mask(S, cfg.series, 0)
+    for algo in ("dissemination", "lf", "bk"):
+        tree = run_scan(fr, cfg.solver, algo)
+        assert np.array_equal(tree.u_pair, seq.u_pair)
+        dev = np.abs(tree.phi0 - seq.phi0)[:, :, mask]
+        print(f"{algo}: max deviation from the sequential order {dev.max():.4f} px")
+        assert dev.max() < 0.05
