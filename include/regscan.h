@@ -1,0 +1,269 @@
+/*
+ * regscan.h - C interface of the MI355X (gfx950) series-registration library.
+ *
+ * The library computes the paper's series registration (Copik et al.,
+ * "Work-stealing prefix scan: addressing load imbalance in large-scale image
+ * registration"): every frame f_k of a series is registered to f_0 by the
+ * prefix scan phi_{0,k} = phi_{0,1} (.) phi_{1,2} (.) ... (.) phi_{k-1,k}
+ * (Section 3), where phi_{i,j} (.) phi_{j,k} = B(phi_ij, phi_jk) registers f_i
+ * and f_k starting from the composition of the two deformations
+ * (Section 2.3.2), and the elements phi_{k-1,k} = A(f_{k-1}, f_k) come from
+ * registrations of consecutive frames started at the identity.
+ *
+ * Registration operator (Section 2.3.1, multilevel gradient flow), in the
+ * dense-displacement form implemented here: phi(x) = x + u(x),
+ *   E(u) = sum_x (T(x + u(x)) - R(x))^2
+ *        + lambda * sum_{c in x,y} sum_x [ (u_c(x+e1) - u_c(x))^2 + (u_c(x+e2) - u_c(x))^2 ]
+ * with forward differences taken only between pixels of the grid, T sampled
+ * bilinearly with edge-clamped taps, minimised by u <- u - tau * dE/du on a
+ * 2x2-box pyramid (coarse to fine).
+ *
+ * Arithmetic is double precision throughout; stored data (images,
+ * displacements, gradients of the float32 entry points) are float32, each
+ * stored value being the double result rounded once.
+ *
+ * Conventions shared by every entry point
+ *   - Images are row-major float [H][W]: x = column, y = row, pixel centres at
+ *     integer coordinates.  Displacements are planar [2][H][W]: plane 0 holds
+ *     the x component, plane 1 the y component, in pixels of that grid.
+ *     Batches stack these along a leading dimension.
+ *   - Every array pointer is DEVICE memory owned by the caller, contiguous,
+ *     4-byte aligned (8-byte for double), unless the description says "host".
+ *     The library never frees caller memory.  It owns a lazily grown
+ *     workspace (pyramids, ping-pong fields, queue, partial sums) that
+ *     reg_release() frees.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     All work is enqueued on it asynchronously; outputs are valid once the
+ *     stream has synchronised.  Entry points returning counts on the host say so.
+ *   - Return value: REG_OK (0) on success; a negative REG_E_* code if the call
+ *     was rejected or failed, with a message from reg_last_error().  Argument
+ *     errors are detected on the host before anything is enqueued.  No C++
+ *     exception crosses this interface.
+ *   - Calls from several host threads are serialised inside the library.
+ */
+#ifndef REGSCAN_H
+#define REGSCAN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+enum {
+  REG_OK = 0,
+  REG_E_INVALID = -1,   /* bad argument: size, pointer, parameter or plan */
+  REG_E_NOMEM = -2,     /* workspace allocation failed */
+  REG_E_HIP = -3,       /* a HIP runtime call failed */
+  REG_E_NODEVICE = -4   /* no usable gfx950 device */
+};
+
+/* per-registration status bits (status[] outputs) */
+enum {
+  REG_S_OK = 0,
+  REG_S_MAXITER = 1,    /* some level used its whole iteration budget without
+                           meeting the relative-decrease rule (not set when the
+                           iteration count is fixed) */
+  REG_S_NONFINITE = 2,  /* the energy became NaN or infinite; the solve stopped
+                           at that iteration and skipped the finer levels */
+  REG_S_ABORTED = 4     /* a batched solve was abandoned by the forward-progress
+                           watchdog; the output is not a solution */
+};
+
+/* scan algorithms (Section 2.1 Table 1; Section 4.1-4.2) */
+enum {
+  SCAN_SEQ = 0,            /* left fold, the sequential recursion */
+  SCAN_DISSEMINATION = 1,  /* Kogge-Stone / Hillis-Steele rounds */
+  SCAN_LADNER_FISCHER = 2, /* P_0 circuit, depth log2 M */
+  SCAN_BRENT_KUNG = 3,     /* up-sweep + down-sweep */
+  SCAN_HIER = 4            /* reduce-then-scan over chunks, global phase with
+                              any of the four algorithms above */
+};
+
+/* execution modes */
+enum {
+  REG_PLAIN = 0,   /* one registration at a time; one kernel launch per
+                      gradient-descent iteration and a host read-back of the
+                      energy for the stopping rule */
+  REG_BATCHED = 1  /* all registrations of a batch (a scan level) in one
+                      persistent launch fed by a device atomic work queue */
+};
+
+/* scan_run flags */
+enum {
+  SCAN_F_GRAPH = 1   /* capture the whole run in a HIP graph on first use and
+                        replay it on later calls with identical arguments */
+};
+
+typedef struct {
+  int32_t levels;      /* pyramid levels L >= 1 (level 0 = full resolution) */
+  int32_t max_iter;    /* gradient-descent iterations per level, >= 1 */
+  int32_t fixed_iter;  /* nonzero: exactly max_iter updates per level */
+  double tau;          /* gradient-descent step, > 0 */
+  double lambda;       /* smoothness weight, >= 0 */
+  double rel_tol;      /* stop a level at iteration t > 0 once
+                          E_{t-1} - E_t <= rel_tol * E_{t-1} */
+} reg_params_t;
+
+/* One operator application (i, j) (.) (j, k) -> (i, k) of a scan plan.
+ * Nodes 0..M-1 are the elements x_1..x_M (x_k = phi_{k-1,k}); node M + n is
+ * the output of op n.  a and b are the input nodes (ranges (i,j) and (j,k)).
+ * level is as-soon-as-possible: 1 + max(level of a, level of b), elements at
+ * level 0.  Ops are sorted by (level, k, i, j). */
+typedef struct {
+  int32_t level, out, a, b, i, j, k;
+} scan_op_t;
+
+/* Text of the last error of this thread (never NULL; "" if none). */
+const char* reg_last_error(void);
+
+/* Interface version (major * 100 + minor). */
+int reg_version(void);
+
+/* Frame pyramid (multilevel scheme, Section 2.3.1): level l+1 is the mean of
+ * 2x2 blocks of level l.
+ *   frames  [N][H][W]             level 0, read only
+ *   pyr     levels 1..L-1 back to back, level l is [N][H>>l][W>>l]
+ *           (sum_{l=1}^{L-1} N*(H>>l)*(W>>l) floats); untouched if L == 1
+ * H and W must be divisible by 2^(L-1) and H>>(L-1), W>>(L-1) >= 8. */
+int reg_pyramid(const float* frames, float* pyr, int N, int H, int W, int levels, void* stream);
+
+/* Deformed template (Definition "Image registration problem", T o phi):
+ *   out[b](x) = T[b](x + u[b](x)), bilinear, edge-clamped taps.
+ *   T [B][H][W], u [B][2][H][W], out [B][H][W] (out must not alias T or u). */
+int reg_warp(const float* T, const float* u, float* out, int B, int H, int W, void* stream);
+int reg_warp_f64(const double* T, const double* u, double* out, int B, int H, int W, void* stream);
+
+/* Transpose of the warp with respect to T (scatter-add of the bilinear taps):
+ *   gT[b][tap(x)] += w_tap(x) * gout[b](x) for the four taps of x + u[b](x).
+ *   gout [B][H][W], u [B][2][H][W], gT [B][H][W] accumulated (not cleared).
+ * Uses atomic additions: the summation order, and so the last bits of gT,
+ * may vary between runs. */
+int reg_warp_adjoint(const float* gout, const float* u, float* gT, int B, int H, int W, void* stream);
+int reg_warp_adjoint_f64(const double* gout, const double* u, double* gT, int B, int H, int W, void* stream);
+
+/* Energy and gradient of the registration functional (one level):
+ *   E[b]      = E(u[b]) for reference R[b], template T[b]     (double, device)
+ *   grad[b]   = dE/du at u[b] (exact away from integer sample positions;
+ *               at an integer position the right-sided derivative), or NULL
+ *   gnorm2[b] = sum_x |grad[b](x)|^2 (double), or NULL
+ *   R, T [B][H][W]; u, grad [B][2][H][W].  Sums are accumulated in double
+ *   in a fixed order (bitwise reproducible). */
+int reg_energy_grad(const float* R, const float* T, const float* u, double lambda,
+                    double* E, float* grad, double* gnorm2, int B, int H, int W, void* stream);
+int reg_energy_grad_f64(const double* R, const double* T, const double* u, double lambda,
+                        double* E, double* grad, double* gnorm2, int B, int H, int W, void* stream);
+
+/* Differentiable warp + energy over a pyramid of `levels` levels:
+ *   E[b] = sum_l E_l with I_a, I_b restricted by 2x2 block means and u by half
+ *   the 2x2 block mean, E_l the functional above with T = I_a^l, R = I_b^l.
+ *   Ia, Ib [B][H][W]; u [B][2][H][W]; E [B] double.  Only the full-resolution
+ *   inputs are read; coarser levels live in library workspace. */
+int reg_pyramid_energy(const float* Ia, const float* u, const float* Ib, double lambda, int levels,
+                       double* E, int B, int H, int W, void* stream);
+int reg_pyramid_energy_f64(const double* Ia, const double* u, const double* Ib, double lambda,
+                           int levels, double* E, int B, int H, int W, void* stream);
+
+/* Backward of reg_pyramid_energy for upstream gradients gE [B] (double):
+ *   dIa = gE * dE/dIa (scatter-add transpose of the gather, restriction
+ *   adjoints), du = gE * dE/du, dIb = gE * dE/dIb = -2 r gE (summed over
+ *   levels).  The pyramid is recomputed, not stored.  dIa, du, dIb are
+ *   overwritten (each may be NULL to skip it); dIa uses atomic additions. */
+int reg_pyramid_energy_backward(const float* Ia, const float* u, const float* Ib, double lambda,
+                                int levels, const double* gE, float* dIa, float* du, float* dIb,
+                                int B, int H, int W, void* stream);
+int reg_pyramid_energy_backward_f64(const double* Ia, const double* u, const double* Ib,
+                                    double lambda, int levels, const double* gE, double* dIa,
+                                    double* du, double* dIb, int B, int H, int W, void* stream);
+
+/* Composition initial guess (Section 2.3.2): displacement of phi_jk o phi_ij,
+ *   out[b](x) = u_ij[b](x) + u_jk[b](x + u_ij[b](x)) per component.
+ *   u_ij, u_jk, out [B][2][H][W]; out must not alias the inputs. */
+int reg_compose(const float* u_ij, const float* u_jk, float* out, int B, int H, int W, void* stream);
+
+/* Restriction to the next coarser grid: out[b] = scale * mean of 2x2 blocks.
+ *   in [B][H][W], out [B][H/2][W/2]; H, W even.  scale = 1 for images, 0.5
+ *   for displacement planes (pass each plane as its own batch item). */
+int reg_restrict(const float* in, float* out, double scale, int B, int H, int W, void* stream);
+
+/* Prolongation of a displacement to the finer grid:
+ *   uf[b](x) = 2 * uc[b]((x - 1/2)/2, (y - 1/2)/2) (bilinear, clamped).
+ *   uc [B][2][Hf/2][Wf/2], uf [B][2][Hf][Wf]; Hf, Wf even. */
+int reg_prolong(const float* uc, float* uf, int B, int Hf, int Wf, void* stream);
+
+/* Batch of multilevel registrations Reg(R = f_ref[b], T = f_tmpl[b], u0[b]):
+ * the initial guess (zero if u0 == NULL) is restricted to the coarsest level,
+ * solved there, and every finer level starts from the prolongation of the
+ * coarser result (Section 2.3.1).  Per level, iteration t evaluates E_t and
+ * the gradient at u_t; unless fixed_iter, the level returns u_t once t > 0 and
+ * E_{t-1} - E_t <= rel_tol * E_{t-1}; otherwise u_{t+1} = u_t - tau * grad.
+ *   frames    [N][H][W]    the series (level 0); coarser levels are built in
+ *                          library workspace on every call
+ *   ref_idx, tmpl_idx [B]  HOST int32 frame indices in [0, N)
+ *   u0        [B][2][H][W] initial guesses or NULL (identity)
+ *   u         [B][2][H][W] results (must not alias u0 or frames)
+ *   iters     [B][levels]  iterations per level (level 0 first), or NULL
+ *   status    [B]          REG_S_* bits, or NULL
+ *   mode      REG_PLAIN or REG_BATCHED; both give bitwise identical results.
+ * REG_PLAIN synchronises the stream after every iteration. */
+int reg_solve_batch(const float* frames, int N, int H, int W,
+                    const int32_t* ref_idx, const int32_t* tmpl_idx,
+                    const float* u0, float* u, int32_t* iters, int32_t* status, int B,
+                    const reg_params_t* p, int mode, void* stream);
+
+/* Plan of the prefix scan over M elements (host only, no GPU use).
+ *   algo        SCAN_*; global_algo is the global phase of SCAN_HIER
+ *               (SCAN_SEQ..SCAN_BRENT_KUNG) and is ignored otherwise
+ *   chunk       SCAN_HIER chunk length (<= 0 or >= M: a single chunk)
+ *   ops         HOST array of `cap` entries, or NULL to query the size
+ *   n_ops       HOST out: number of ops;  n_levels: HOST out: plan depth
+ * For SCAN_LADNER_FISCHER / SCAN_BRENT_KUNG (and those global phases) with a
+ * size that is not a power of two, the circuit is built for the next power of
+ * two and ops ending beyond the last element are dropped.
+ * Returns REG_E_INVALID if cap is too small (n_ops is still set). */
+int scan_plan(int M, int algo, int chunk, int global_algo, scan_op_t* ops, int cap,
+              int* n_ops, int* n_levels);
+
+/* Register every frame of a series to frame 0 (Section 3):
+ *   phase A   u_pair[k-1] = A(f_{k-1}, f_k), k = 1..M, M = N - 1, one batch;
+ *   scan      the plan of (algo, chunk, global_algo) level by level, each level
+ *             one batch of B(phi_ij, phi_jk) registrations (REG_BATCHED: one
+ *             persistent launch per level; REG_PLAIN: one registration at a
+ *             time).
+ *   frames   [N][H][W], N >= 2
+ *   phi0     [M][2][H][W]  out: u_{0,k} for k = 1..M
+ *   u_pair   [M][2][H][W]  out: u_{k-1,k}, or NULL (kept in workspace)
+ *   op_iters [M + n_ops][levels] out: iterations of the A registrations
+ *            (k = 1..M) then of the plan's ops in plan order, or NULL
+ *   status   [M + n_ops] out: REG_S_* bits in the same order, or NULL
+ *   flags    SCAN_F_* bits
+ * Intermediate scan nodes live in library workspace, reused once dead. */
+int scan_run(const float* frames, int N, int H, int W, const reg_params_t* p,
+             int algo, int chunk, int global_algo, int mode, int flags,
+             float* phi0, float* u_pair, int32_t* op_iters, int32_t* status, void* stream);
+
+/* Kernel-duration probe: total device time in milliseconds of the persistent
+ * solve launches of the last scan_run / reg_solve_batch in REG_BATCHED mode
+ * (HIP events recorded around every launch on the launch stream), and the
+ * number of launches.  HOST outputs; waits for those events. */
+int reg_last_solve_timing(double* total_ms, int* launches);
+
+/* Library tuning: tile height (rows per tile, multiple of 4, 4..64) of the
+ * gradient-descent sweep, and the cap on workgroups per registration in
+ * batched mode.  0 keeps the current value.  Both are chosen automatically
+ * (see reg_autotune) unless set here. */
+int reg_set_tuning(int tile_rows, int max_group);
+
+/* Time candidate tile heights and group caps on the given batch shape with
+ * fixed-iteration solves and keep the fastest (HOST outputs, optional). */
+int reg_autotune(int H, int W, int levels, int batch, int* tile_rows, int* max_group, void* stream);
+
+/* Free the library workspace and cached graphs. */
+void reg_release(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* REGSCAN_H */

@@ -20,10 +20,14 @@ pyramid.  T is sampled bilinearly with edge-clamped taps.
 Array conventions: images [H][W] (row y, column x), displacements [2][H][W]
 with plane 0 = x and plane 1 = y, pixel centres on integer coordinates.
 
-Reading taken where the kernel and the oracle must agree on an integer
-decision: the integer part of a displacement (which bilinear cell a sample
-falls in) is decided on the float32 value of that displacement, the
-precision of the GPU kernels; everything else is float64.
+Storage precision.  Stored data are 32-bit floats: the frames, their pyramid
+levels, and every displacement field the solver keeps (the initial guess on
+the coarsest level, each gradient-descent iterate, each prolongation) - the
+paper moves a deformation as single-precision floats (Section 5: 20 bytes of
+deformation data and indices per message).  All arithmetic is float64; a
+stored value is the float64 result rounded to float32 (``f32``).  The integer
+part of a displacement (which bilinear cell a sample falls in) is therefore
+decided on a float32 value.
 """
 from __future__ import annotations
 
@@ -39,6 +43,11 @@ STATUS_NONFINITE = 2   # the energy became NaN or infinite; the task stopped
 # ----------------------------------------------------------------------------
 # Bilinear sampling
 # ----------------------------------------------------------------------------
+
+def f32(a):
+    """Round to the float32 storage format (returned as float64)."""
+    return np.asarray(a, dtype=np.float64).astype(np.float32).astype(np.float64)
+
 
 def split_offset(off):
     """Integer cell offset (decided in float32) and the float64 remainder."""
@@ -134,9 +143,11 @@ def restrict_field(u):
 
 
 def pyramid(F, levels):
-    out = [np.asarray(F, dtype=np.float64)]
+    """Stored frame pyramid: each level is the 2x2 block mean of the stored
+    level below, rounded to float32."""
+    out = [f32(F)]
     for _ in range(levels - 1):
-        out.append(restrict_image(out[-1]))
+        out.append(f32(restrict_image(out[-1])))
     return out
 
 
@@ -169,10 +180,11 @@ def solve_level(R, T, u0, tau, lam, max_iter, fixed_iter, rel_tol):
     Iteration t evaluates E_t and g_t at u_t.  Unless the iteration count is
     fixed, the solve returns u_t as soon as t > 0 and the relative decrease
     E_{t-1} - E_t is at most rel_tol * E_{t-1} (this includes any increase);
-    otherwise it steps u_{t+1} = u_t - tau g_t.  After max_iter steps it
-    returns u_{max_iter}.  A non-finite energy stops the solve at once.
+    otherwise it steps u_{t+1} = u_t - tau g_t (stored in float32).  After
+    max_iter steps it returns u_{max_iter}.  A non-finite energy stops the
+    solve at once.
     """
-    u = np.array(u0, dtype=np.float64, copy=True)
+    u = f32(u0)
     e_prev = None
     energies = []
     for t in range(max_iter):
@@ -183,7 +195,7 @@ def solve_level(R, T, u0, tau, lam, max_iter, fixed_iter, rel_tol):
         if not fixed_iter and e_prev is not None and (e_prev - E) <= rel_tol * e_prev:
             return LevelResult(u, t, STATUS_OK, energies)
         e_prev = E
-        u = u - tau * g
+        u = f32(u - tau * g)
     status = STATUS_OK if fixed_iter else STATUS_MAXITER
     return LevelResult(u, max_iter, status, energies)
 
@@ -210,17 +222,21 @@ def register(R_pyr, T_pyr, u0, params):
         u = np.array(u0, dtype=np.float64)
         for _ in range(L - 1):
             u = restrict_field(u)
+        u = f32(u)
     iters = [0] * L
     status = STATUS_OK
     for lvl in range(L - 1, -1, -1):
         if lvl < L - 1:
             h, w = R_pyr[lvl].shape
-            u = prolong_field(u, h, w)
+            u = f32(prolong_field(u, h, w))
         res = solve_level(R_pyr[lvl], T_pyr[lvl], u, params.tau, params.lam,
                           params.max_iter, params.fixed_iter, params.rel_tol)
         u, iters[lvl] = res.u, res.iters
         status |= res.status
         if res.status & STATUS_NONFINITE:
+            # a diverged registration has no meaningful field: report NaN
+            h0, w0 = R_pyr[0].shape
+            u = np.full((2, h0, w0), np.nan)
             break
     return RegResult(u, iters, status)
 

@@ -1,0 +1,98 @@
+// Device helpers shared by the registration kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rs {
+
+constexpr int kWG = 256;        // threads of every tile workgroup (4 wavefronts)
+constexpr int kWave = 64;
+constexpr int kTileW = 64;      // a tile row is one wavefront wide
+constexpr int kMaxLevels = 8;
+constexpr int kRB = 4;          // rows per register batch in the sweep
+
+__host__ __device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// Stopping rule of a level (relative energy decrease), shared by the device
+// solver and the host loop of the plain path so both decide identically.
+__host__ __device__ inline bool level_stops(double e_prev, double e, double rel_tol) {
+  return (e_prev - e) <= rel_tol * e_prev;
+}
+
+// Integer cell and in-cell fraction of a displacement component.  The cell is
+// decided on the float32 value; the fraction u - floor(u) is exact.  All
+// arithmetic of the kernels is double; stored data are float (or double in
+// the float64 instantiations).
+__device__ __forceinline__ void cell_of(float u, int& c, double& f) {
+  float fl = floorf(u);
+  fl = fminf(fmaxf(fl, -1048576.f), 1048576.f);   // NaN -> -2^20: taps clamp, value stays NaN
+  c = (int)fl;
+  f = (double)(u - fl);
+}
+__device__ __forceinline__ void cell_of(double u, int& c, double& f) {
+  float fl = floorf((float)u);
+  fl = fminf(fmaxf(fl, -1048576.f), 1048576.f);
+  c = (int)fl;
+  f = u - (double)fl;
+}
+
+// Bilinear sample of img [H][W] at (x0 + wx, y0 + wy) with edge-clamped taps,
+// and its derivatives with respect to the sample position.
+template <typename S>
+__device__ __forceinline__ void bilin(const S* __restrict__ img, int H, int W, int x0, int y0,
+                                      double wx, double wy, double& s, double& dsx, double& dsy) {
+  const int xa = clampi(x0, 0, W - 1), xb = clampi(x0 + 1, 0, W - 1);
+  const int ya = clampi(y0, 0, H - 1), yb = clampi(y0 + 1, 0, H - 1);
+  const double i00 = img[ya * W + xa], i01 = img[ya * W + xb];
+  const double i10 = img[yb * W + xa], i11 = img[yb * W + xb];
+  const double ox = 1.0 - wx, oy = 1.0 - wy;
+  s = oy * (ox * i00 + wx * i01) + wy * (ox * i10 + wx * i11);
+  dsx = oy * (i01 - i00) + wy * (i11 - i10);
+  dsy = ox * (i10 - i00) + wx * (i11 - i01);
+}
+
+template <typename S>
+__device__ __forceinline__ double bilin_value(const S* __restrict__ img, int H, int W, int x0, int y0,
+                                              double wx, double wy) {
+  const int xa = clampi(x0, 0, W - 1), xb = clampi(x0 + 1, 0, W - 1);
+  const int ya = clampi(y0, 0, H - 1), yb = clampi(y0 + 1, 0, H - 1);
+  const double ox = 1.0 - wx, oy = 1.0 - wy;
+  return oy * (ox * (double)img[ya * W + xa] + wx * (double)img[ya * W + xb]) +
+         wy * (ox * (double)img[yb * W + xa] + wx * (double)img[yb * W + xb]);
+}
+
+// Butterfly sum over the 64 lanes of a wavefront: every lane ends with the
+// same, order-fixed total.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// Canonical order-fixed sum of n doubles by one wavefront: lane l adds
+// p[l], p[l+64], ... in sequence, then the butterfly.  Used for every
+// per-tile energy total so that all execution paths agree bitwise.
+__device__ __forceinline__ double wave_sum_array(const double* p, int n, int lane) {
+  double acc = 0.0;
+  for (int i = lane; i < n; i += kWave) acc += p[i];
+  return wave_sum(acc);
+}
+
+// Block-wide order-fixed sum of one double per thread (kWG threads); the
+// result is valid in thread 0.  `red` is __shared__ double[kWG / kWave].
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) red[wave] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int w = 0; w < kWG / kWave; ++w) t += red[w];
+  }
+  __syncthreads();
+  return t;
+}
+
+}  // namespace rs

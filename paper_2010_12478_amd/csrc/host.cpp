@@ -1,0 +1,797 @@
+// C interface of the registration library: argument validation, workspace,
+// batch / scan orchestration and the plain and batched execution paths.
+#include "../../include/regscan.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+#include "plan.h"
+#include "sweep.h"
+
+using namespace rs;
+
+namespace {
+
+thread_local std::string g_err;
+std::recursive_mutex g_mu;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess) return fail(REG_E_HIP, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+#define TRY(expr)          \
+  do {                     \
+    int r_ = (expr);       \
+    if (r_ != REG_OK) return r_; \
+  } while (0)
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t n = 0;
+};
+
+struct State {
+  bool init = false;
+  int device = -1;
+  int n_cu = 0;
+  int blocks_per_cu = 0;
+  int tile_rows = 32;
+  int max_group = 16;
+  unsigned spin_limit = 1u << 22;   // ~seconds of polling before the watchdog aborts a run
+  DevBuf pyr, slots, part, ctrl, tasks, nodes, upair, iters, status, misc, lvl;
+  double* h_E = nullptr;   // pinned host scalar for the plain path
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+  size_t events_used = 0;
+  unsigned generation = 0;   // bumps whenever a workspace buffer moves
+};
+
+State g;
+
+int ensure_device() {
+  if (g.init) return REG_OK;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n == 0) return fail(REG_E_NODEVICE, "no HIP device available");
+  HIPCHK(hipGetDevice(&g.device));
+  hipDeviceProp_t prop;
+  HIPCHK(hipGetDeviceProperties(&prop, g.device));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(REG_E_NODEVICE, "device %s is not gfx950 (this library is built for gfx950 only)",
+                prop.gcnArchName);
+  g.n_cu = prop.multiProcessorCount;
+  int nb = 0;
+  HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, persistent_kernel(), kWG, 0));
+  if (nb < 1) return fail(REG_E_HIP, "persistent kernel cannot be resident");
+  g.blocks_per_cu = nb;
+  HIPCHK(hipHostMalloc((void**)&g.h_E, sizeof(double), hipHostMallocDefault));
+  g.init = true;
+  return REG_OK;
+}
+
+int ensure(DevBuf& b, size_t bytes) {
+  if (b.n >= bytes) return REG_OK;
+  if (b.p) {
+    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(hipFree(b.p));
+    b.p = nullptr;
+    b.n = 0;
+  }
+  size_t want = std::max(bytes, (size_t)256);
+  if (hipMalloc(&b.p, want) != hipSuccess) {
+    (void)hipGetLastError();
+    b.p = nullptr;
+    return fail(REG_E_NOMEM, "workspace allocation of %zu bytes failed", want);
+  }
+  b.n = want;
+  g.generation++;
+  return REG_OK;
+}
+
+int check_dims(int B, int H, int W) {
+  if (B < 0) return fail(REG_E_INVALID, "batch size %d < 0", B);
+  if (H < 1 || W < 1) return fail(REG_E_INVALID, "image size %dx%d must be positive", H, W);
+  if (H > 16384 || W > 16384 || (long long)H * W > (1LL << 28))
+    return fail(REG_E_INVALID, "image size %dx%d exceeds 16384 per side or 2^28 pixels", H, W);
+  return REG_OK;
+}
+
+int check_params(const reg_params_t* p, int H, int W) {
+  if (!p) return fail(REG_E_INVALID, "params is NULL");
+  if (p->levels < 1 || p->levels > kMaxLevels) return fail(REG_E_INVALID, "levels %d not in [1, %d]", p->levels, kMaxLevels);
+  if (p->max_iter < 1) return fail(REG_E_INVALID, "max_iter %d < 1", p->max_iter);
+  if (!(p->tau > 0.0) || !std::isfinite(p->tau)) return fail(REG_E_INVALID, "tau must be positive and finite");
+  if (!(p->lambda >= 0.0) || !std::isfinite(p->lambda)) return fail(REG_E_INVALID, "lambda must be >= 0 and finite");
+  if (!(p->rel_tol >= 0.0) || !std::isfinite(p->rel_tol)) return fail(REG_E_INVALID, "rel_tol must be >= 0 and finite");
+  const int F = 1 << (p->levels - 1);
+  if (H % F || W % F) return fail(REG_E_INVALID, "%dx%d is not divisible by 2^(levels-1) = %d", H, W, F);
+  if (H / F < 8 || W / F < 8) return fail(REG_E_INVALID, "coarsest level %dx%d is below 8 px", H / F, W / F);
+  return REG_OK;
+}
+
+hipEvent_t* next_events() {
+  if (g.events_used == g.events.size()) {
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return nullptr;
+    g.events.push_back({a, b});
+  }
+  return &g.events[g.events_used++].first;
+}
+
+// ------------------------------------------------------------------ pyramid
+
+// Levels 1..L-1 of all N frames into g.pyr; fills pyr pointers.
+int build_pyramid(const float* frames, int N, int H, int W, int L, const float* lv[kMaxLevels], hipStream_t s) {
+  size_t total = 0;
+  for (int l = 1; l < L; ++l) total += (size_t)N * (H >> l) * (W >> l);
+  TRY(ensure(g.pyr, total * sizeof(float)));
+  lv[0] = frames;
+  float* p = (float*)g.pyr.p;
+  for (int l = 1; l < L; ++l) {
+    HIPCHK(launch_restrict(lv[l - 1], p, 1.0, N, H >> (l - 1), W >> (l - 1), false, s));
+    lv[l] = p;
+    p += (size_t)N * (H >> l) * (W >> l);
+  }
+  return REG_OK;
+}
+
+SolveArgs base_args(const float* const lv[kMaxLevels], int H, int W, const reg_params_t* p) {
+  SolveArgs a;
+  std::memset(&a, 0, sizeof a);
+  for (int l = 0; l < kMaxLevels; ++l) a.pyr[l] = l < p->levels ? lv[l] : nullptr;
+  a.H = H;
+  a.W = W;
+  a.levels = p->levels;
+  a.max_iter = p->max_iter;
+  a.fixed_iter = p->fixed_iter ? 1 : 0;
+  a.tau = p->tau;
+  a.lam = p->lambda;
+  a.rel_tol = p->rel_tol;
+  a.th = g.tile_rows;
+  a.max_tiles = tiles_of(H, W, g.tile_rows);
+  a.slot_floats = slot_floats_for(H, W, p->levels, a.lvl_off, &a.bufB_off);
+  a.spin_limit = g.spin_limit;
+  return a;
+}
+
+// ------------------------------------------------------------ batched path
+
+struct Launch {
+  int g, groups, grid;
+};
+
+Launch plan_launch(int n_tasks, int H, int W) {
+  const int resident = g.blocks_per_cu * g.n_cu;
+  const int tiles = tiles_of(H, W, g.tile_rows);
+  int gs = 1;
+  while (gs * 2 <= g.max_group && gs * 2 <= tiles && (long long)n_tasks * gs * 2 <= resident &&
+         8 * gs * 2 <= resident)
+    gs *= 2;
+  int groups = std::min(resident / gs, ((n_tasks + 7) / 8) * 8);
+  groups = std::max(8, (groups / 8) * 8);
+  return {gs, groups, groups * gs};
+}
+
+// Runs n tasks (device descriptors) with one persistent launch.
+int run_batched(SolveArgs a, const TaskDesc* d_tasks, int n, hipStream_t s, bool timed) {
+  if (n == 0) return REG_OK;
+  const Launch L = plan_launch(n, a.H, a.W);
+  const int ctrl_ints = 64 + 32 * L.groups;
+  TRY(ensure(g.ctrl, (size_t)ctrl_ints * sizeof(int)));
+  TRY(ensure(g.part, (size_t)L.groups * 2 * a.max_tiles * sizeof(double)));
+  TRY(ensure(g.slots, (size_t)L.groups * a.slot_floats * sizeof(float)));
+  a.tasks = d_tasks;
+  a.n_tasks = n;
+  a.g = L.g;
+  a.ctrl = (int*)g.ctrl.p;
+  a.part = (double*)g.part.p;
+  a.ws = (float*)g.slots.p;
+  HIPCHK(launch_reset_tasks(a.ctrl, ctrl_ints, d_tasks, n, s));
+  hipEvent_t* ev = timed ? next_events() : nullptr;
+  if (ev) HIPCHK(hipEventRecord(ev[0], s));
+  HIPCHK(launch_persistent(a, L.grid, s));
+  if (ev) HIPCHK(hipEventRecord(ev[1], s));
+  return REG_OK;
+}
+
+// -------------------------------------------------------------- plain path
+
+int run_plain(SolveArgs a, const std::vector<TaskDesc>& tasks, const TaskDesc* d_tasks, hipStream_t s) {
+  TRY(ensure(g.slots, a.slot_floats * sizeof(float)));
+  TRY(ensure(g.part, (size_t)(a.max_tiles + 1) * sizeof(double)));
+  float* slot = (float*)g.slots.p;
+  double* part = (double*)g.part.p;
+  double* dE = part + a.max_tiles;
+  const int L = a.levels;
+  std::vector<int32_t> iters(L);
+  for (size_t b = 0; b < tasks.size(); ++b) {
+    const TaskDesc& d = tasks[b];
+    auto start = [&](int l) -> float* { return l == 0 ? d.out : slot + a.lvl_off[l]; };
+    float* cur = start(L - 1);
+    HIPCHK(launch_plain_init(d_tasks + b, a, cur, s));
+    float* bufB = slot + a.bufB_off;
+    int32_t status = 0;
+    bool dead = false;
+    for (int l = L - 1; l >= 0; --l) {
+      iters[l] = 0;
+      if (dead) continue;
+      const int h = a.H >> l, w = a.W >> l;
+      if (l < L - 1) {
+        HIPCHK(launch_plain_prolong(cur, start(l), h, w, s));
+        cur = start(l);
+      }
+      float* other = bufB;
+      const float* R = a.pyr[l] + (size_t)d.ref * h * w;
+      const float* T = a.pyr[l] + (size_t)d.tmpl * h * w;
+      const int nt = tiles_of(h, w, a.th);
+      double e_prev = 0.0;
+      int it = 0;
+      for (; it < a.max_iter; ++it) {
+        HIPCHK(launch_plain_sweep(R, T, cur, other, h, w, a.tau, a.lam, a.th, part, s));
+        HIPCHK(launch_plain_reduce(part, nt, dE, s));
+        HIPCHK(hipMemcpyAsync(g.h_E, dE, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        const double E = *g.h_E;
+        if (!std::isfinite(E)) {
+          status |= REG_S_NONFINITE;
+          dead = true;
+          break;
+        }
+        if (!a.fixed_iter && it > 0 && level_stops(e_prev, E, a.rel_tol)) break;
+        e_prev = E;
+        std::swap(cur, other);
+      }
+      iters[l] = it;
+      if (it == a.max_iter && !a.fixed_iter) status |= REG_S_MAXITER;
+    }
+    const size_t nf = (size_t)2 * a.H * a.W;
+    if (dead)
+      HIPCHK(launch_copy(nullptr, d.out, nf, s));
+    else if (cur != d.out)
+      HIPCHK(launch_copy(cur, d.out, nf, s));
+    if (d.iters) HIPCHK(hipMemcpyAsync(d.iters, iters.data(), L * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    if (d.status) HIPCHK(hipMemcpyAsync(d.status, &status, sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));   // host staging of iters/status must outlive the copies
+  }
+  return REG_OK;
+}
+
+int upload_tasks(DevBuf& buf, const std::vector<TaskDesc>& t, hipStream_t s) {
+  if (t.empty()) return REG_OK;
+  TRY(ensure(buf, t.size() * sizeof(TaskDesc)));
+  HIPCHK(hipMemcpyAsync(buf.p, t.data(), t.size() * sizeof(TaskDesc), hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return REG_OK;
+}
+
+}  // namespace
+
+namespace rs {
+size_t slot_floats_for(int H, int W, int levels, size_t* lvl_off, size_t* bufB_off) {
+  size_t off = 0;
+  for (int l = 0; l < kMaxLevelsHost; ++l) lvl_off[l] = 0;
+  for (int l = 1; l < levels; ++l) {
+    lvl_off[l] = off;
+    off += (size_t)2 * (H >> l) * (W >> l);
+  }
+  *bufB_off = off;
+  off += (size_t)2 * H * W;
+  return (off + 63) & ~(size_t)63;
+}
+}  // namespace rs
+
+// ===================================================================== C ABI
+
+extern "C" {
+
+const char* reg_last_error(void) { return g_err.c_str(); }
+
+int reg_version(void) { return 100; }
+
+int reg_pyramid(const float* frames, float* pyr, int N, int H, int W, int levels, void* stream) {
+  std::lock_guard<std::recursive_mutex> lk(g_mu);
+  TRY(check_dims(N, H, W));
+  if (levels < 1 || levels > kMaxLevels) return fail(REG_E_INVALID, "levels %d not in [1, %d]", levels, kMaxLevels);
+  const int F = 1 << (levels - 1);
+  if (H % F || W % F || H / F < 8 || W / F < 8)
+    return fail(REG_E_INVALID, "%dx%d cannot hold %d levels (divisible by %d, coarsest >= 8 px)", H, W, levels, F);
+  if (N == 0 || levels == 1) return REG_OK;
+  if (!frames || !pyr) return fail(REG_E_INVALID, "NULL pointer");
+  TRY(ensure_device());
+  hipStream_t s = (hipStream_t)stream;
+  const float* src = frames;
+  float* dst = pyr;
+  for (int l = 1; l < levels; ++l) {
+    HIPCHK(launch_restrict(src, dst, 1.0, N, H >> (l - 1), W >> (l - 1), false, s));
+    src = dst;
+    dst += (size_t)N * (H >> l) * (W >> l);
+  }
+  return REG_OK;
+}
+
+static int warp_common(const void* T, const void* u, void* out, int B, int H, int W, void* stream, bool f64) {
+  std::lock_guard<std::recursive_mutex> lk(g_mu);
+  TRY(check_dims(B, H, W));
+  if (B == 0) return REG_OK;
+  if (!T || !u || !out) return fail(REG_E_INVALID, "NULL pointer");
+  if (out == T || out == u) return fail(REG_E_INVALID, "out aliases an input");
+  TRY(ensure_device());
+  HIPCHK(launch_warp(T, u, out, B, H, W, f64, (hipStream_t)stream));
+  return REG_OK;
+}
+
+int reg_warp(const float* T, const float* u, float* out, int B, int H, int W, void* stream) {
+  return warp_common(T, u, out, B, H, W, stream, false);
+}
+int reg_warp_f64(const double* T, const double* u, double* out, int B, int H, int W, void* stream) {
+  return warp_common(T, u, out, B, H, W, stream, true);
+}
+
+static int adjoint_common(const void* gout, const void* u, void* gT, int B, int H, int W, void* stream, bool f64) {
+  std::lock_guard<std::recursive_mutex> lk(g_mu);
+  TRY(check_dims(B, H, W));
+  if (B == 0) return REG_OK;
+  if (!gout || !u || !gT) return fail(REG_E_INVALID, "NULL pointer");
+  TRY(ensure_device());
+  HIPCHK(launch_warp_adjoint(gout, u, gT, B, H, W, f64, (hipStream_t)stream));
+  return REG_OK;
+}
+
+int reg_warp_adjoint(const float* gout, const float* u, float* gT, int B, int H, int W, void* stream) {
+  return adjoint_common(gout, u, gT, B, H, W, stream, false);
+}
+int reg_warp_adjoint_f64(const double* gout, const double* u, double* gT, int B, int H, int W, void* stream) {
+  return adjoint_common(gout, u, gT, B, H, W, stream, true);
+}
+
+static int energy_common(const void* R, const void* T, const void* u, double lam, double* E, void* grad,
+                         double* gnorm2, int B, int H, int W, void* stream, bool f64) {
+  std::lock_guard<std::recursive_mutex> lk(g_mu);
+  TRY(check_dims(B, H, W));
+  if (B == 0) return REG_OK;
+  if (!R || !T || !u || !E) return fail(REG_E_INVALID, "NULL pointer");
+  if (!(lam >= 0.0) || !std::isfinite(lam)) return fail(REG_E_INVALID, "lambda must be >= 0 and finite");
+  TRY(ensure_device());
+  const int th = g.tile_rows;
+  const size_t nt = (size_t)tiles_of(H, W, th);
+  TRY(ensure(g.misc, (size_t)2 * B * nt * sizeof(double)));
+  HIPCHK(launch_energy_grad(R, T, u, lam, E, grad, gnorm2, B, H, W, th, (double*)g.misc.p, f64,
+                            (hipStream_t)stream));
+  return REG_OK;
+}
+
+int reg_energy_grad(const float* R, const float* T, const float* u, double lambda, double* E, float* grad,
+                    double* gnorm2, int B, int H, int W, void* stream) {
+  return energy_common(R, T, u, lambda, E, grad, gnorm2, B, H, W, stream, false);
+}
+int reg_energy_grad_f64(const double* R, const double* T, const double* u, double lambda, double* E,
+                        double* grad, double* gnorm2, int B, int H, int W, void* stream) {
+  return energy_common(R, T, u, lambda, E, grad, gnorm2, B, H, W, stream, true);
+}
+
+// Coarser levels of (Ia, u, Ib) for the differentiable energy, in g.lvl:
+// per level l >= 1: Ia_l, Ib_l [B][h][w], u_l [B][2][h][w], and gradient
+// buffers dIa_l, dIb_l, du_l of the same shapes.
+struct PyrLevels {
+  const void* Ia[kMaxLevels];
+  const void* Ib[kMaxLevels];
+  const void* u[kMaxLevels];
+  void* dIa[kMaxLevels];
+  void* dIb[kMaxLevels];
+  void* du[kMaxLevels];
+};
+
+static int pyramid_levels(const void* Ia, const void* u, const void* Ib, int levels, int B, int H, int W,
+                          bool f64, bool grads, PyrLevels& P, hipStream_t s) {
+  const size_t es = f64 ? 8 : 4;
+  size_t total = 0;
+  for (int l = 1; l < levels; ++l) total += (size_t)B * (H >> l) * (W >> l) * (grads ? 8 : 4);
+  TRY(ensure(g.lvl, total * es + 256));
+  char* p = (char*)g.lvl.p;
+  P.Ia[0] = Ia;
+  P.Ib[0] = Ib;
+  P.u[0] = u;
+  for (int l = 1; l < levels; ++l) {
+    const size_t n = (size_t)B * (H >> l) * (W >> l);
+    void* a = p;
+    p += n * es;
+    void* b = p;
+    p += n * es;
+    void* v = p;
+    p += 2 * n * es;
+    HIPCHK(launch_restrict(P.Ia[l - 1], a, 1.0, B, H >> (l - 1), W >> (l - 1), f64, s));
+    HIPCHK(launch_restrict(P.Ib[l - 1], b, 1.0, B, H >> (l - 1), W >> (l - 1), f64, s));
+    HIPCHK(launch_restrict(P.u[l - 1], v, 0.5, 2 * B, H >> (l - 1), W >> (l - 1), f64, s));
+    P.Ia[l] = a;
+    P.Ib[l] = b;
+    P.u[l] = v;
+    if (grads) {
+      P.dIa[l] = p;
+      p += n * es;
+      P.dIb[l] = p;
+      p += n * es;
+      P.du[l] = p;
+      p += 2 * n * es;
+    }
+  }
+  return REG_OK;
+}
+
+static int pyr_check(int levels, int B, int H, int W) {
+  TRY(check_dims(B, H, W));
+  if (levels < 1 || levels > kMaxLevels) return fail(REG_E_INVALID, "levels %d not in [1, %d]", levels, kMaxLevels);
+  const int F = 1 << (levels - 1);
+  if (H % F || W % F) return fail(REG_E_INVALID, "%dx%d is not divisible by %d", H, W, F);
+  return REG_OK;
+}
+
+static int pyr_energy_common(const void* Ia, const void* u, const void* Ib, double lam, int levels, double* E,
+                             int B, int H, int W, void* stream, bool f64) {
+  std::lock_guard<std::recursive_mutex> lk(g_mu);
+  TRY(pyr_check(levels, B, H, W));
+  if (B == 0) return REG_OK;
+  if (!Ia || !u || !Ib || !E) return fail(REG_E_INVALID, "NULL pointer");
+  if (!(lam >= 0.0) || !std::isfinite(lam)) return fail(REG_E_INVALID, "lambda must be >= 0 and finite");
+  TRY(ensure_device());
+  hipStream_t s = (hipStream_t)stream;
+  PyrLevels P;
+  TRY(pyramid_levels(Ia, u, Ib, levels, B, H, W, f64, false, P, s));
+  const int th = g.tile_rows;
+  const size_t nt = (size_t)tiles_of(H, W, th);
+  TRY(ensure(g.misc, ((size_t)2 * B * nt + B) * sizeof(double)));
+  double* part = (double*)g.misc.p;
+  double* El = part + 2 * B * nt;
+  for (int l = 0; l < levels; ++l) {
+    HIPCHK(launch_energy_grad(P.Ib[l], P.Ia[l], P.u[l], lam, El, nullptr, nullptr, B, H >> l, W >> l, th, part,
+                              f64, s));
+    HIPCHK(launch_add_energy(El, E, B, l == 0, s));
+  }
+  return REG_OK;
+}
+
+int reg_pyramid_energy(const float* Ia, const float* u, const float* Ib, double lambda, int levels, double* E,
+                       int B, int H, int W, void* stream) {
+  return pyr_energy_common(Ia, u, Ib, lambda, levels, E, B, H, W, stream, false);
+}
+int reg_pyramid_energy_f64(const double* Ia, const double* u, const double* Ib, double lambda, int levels,
+                           double* E, int B, int H, int W, void* stream) {
+  return pyr_energy_common(Ia, u, Ib, lambda, levels, E, B, H, W, stream, true);
+}
+
+static int pyr_backward_common(const void* Ia, const void* u, const void* Ib, double lam, int levels,
+                               const double* gE, void* dIa, void* du, void* dIb, int B, int H, int W,
+                               void* stream, bool f64) {
+  std::lock_guard<std::recursive_mutex> lk(g_mu);
+  TRY(pyr_check(levels, B, H, W));
+  if (B == 0) return REG_OK;
+  if (!Ia || !u || !Ib || !gE) return fail(REG_E_INVALID, "NULL pointer");
+  if (!(lam >= 0.0) || !std::isfinite(lam)) return fail(REG_E_INVALID, "lambda must be >= 0 and finite");
+  TRY(ensure_device());
+  hipStream_t s = (hipStream_t)stream;
+  PyrLevels P;
+  TRY(pyramid_levels(Ia, u, Ib, levels, B, H, W, f64, true, P, s));
+  const size_t es = f64 ? 8 : 4;
+  const size_t n0 = (size_t)B * H * W;
+  // level-0 outputs the caller skipped go to scratch
+  TRY(ensure(g.misc, 4 * n0 * es));
+  char* scratch = (char*)g.misc.p;
+  P.dIa[0] = dIa ? dIa : (void*)scratch;
+  P.dIb[0] = dIb ? dIb : (void*)(scratch + n0 * es);
+  P.du[0] = du ? du : (void*)(scratch + 2 * n0 * es);
+  for (int l = levels - 1; l >= 0; --l) {
+    const bool top = l == levels - 1;
+    HIPCHK(launch_adjoint_init(top ? nullptr : P.dIa[l + 1], P.dIa[l], B, H >> l, W >> l, f64, s));
+    HIPCHK(launch_energy_backward_level(P.Ia[l], P.u[l], P.Ib[l], lam, gE, P.dIa[l], P.du[l], P.dIb[l],
+                                        top ? nullptr : P.du[l + 1], top ? nullptr : P.dIb[l + 1], B, H >> l,
+                                        W >> l, f64, s));
+  }
+  return REG_OK;
+}
+
+int reg_pyramid_energy_backward(const float* Ia, const float* u, const float* Ib, double lambda, int levels,
+                                const double* gE, float* dIa, float* du, float* dIb, int B, int H, int W,
+                                void* stream) {
+  return pyr_backward_common(Ia, u, Ib, lambda, levels, gE, dIa, du, dIb, B, H, W, stream, false);
+}
+int reg_pyramid_energy_backward_f64(const double* Ia, const double* u, const double* Ib, double lambda,
+                                    int levels, const double* gE, double* dIa, double* du, double* dIb, int B,
+                                    int H, int W, void* stream) {
+  return pyr_backward_common(Ia, u, Ib, lambda, levels, gE, dIa, du, dIb, B, H, W, stream, true);
+}
+
+int reg_compose(const float* u_ij, const float* u_jk, float* out, int B, int H, int W, void* stream) {
+  std::lock_guard<std::recursive_mutex> lk(g_mu);
+  TRY(check_dims(B, H, W));
+  if (B == 0) return REG_OK;
+  if (!u_ij || !u_jk || !out) return fail(REG_E_INVALID, "NULL pointer");
+  if (out == u_ij || out == u_jk) return fail(REG_E_INVALID, "out aliases an input");
+  TRY(ensure_device());
+  HIPCHK(launch_compose(u_ij, u_jk, out, B, H, W, (hipStream_t)stream));
+  return REG_OK;
+}
+
+int reg_restrict(const float* in, float* out, double scale, int B, int H, int W, void* stream) {
+  std::lock_guard<std::recursive_mutex> lk(g_mu);
+  TRY(check_dims(B, H, W));
+  if (H % 2 || W % 2) return fail(REG_E_INVALID, "%dx%d is not even", H, W);
+  if (B == 0) return REG_OK;
+  if (!in || !out) return fail(REG_E_INVALID, "NULL pointer");
+  TRY(ensure_device());
+  HIPCHK(launch_restrict(in, out, scale, B, H, W, false, (hipStream_t)stream));
+  return REG_OK;
+}
+
+int reg_prolong(const float* uc, float* uf, int B, int Hf, int Wf, void* stream) {
+  std::lock_guard<std::recursive_mutex> lk(g_mu);
+  TRY(check_dims(B, Hf, Wf));
+  if (Hf % 2 || Wf % 2) return fail(REG_E_INVALID, "%dx%d is not even", Hf, Wf);
+  if (B == 0) return REG_OK;
+  if (!uc || !uf) return fail(REG_E_INVALID, "NULL pointer");
+  TRY(ensure_device());
+  HIPCHK(launch_prolong(uc, uf, B, Hf, Wf, (hipStream_t)stream));
+  return REG_OK;
+}
+
+int reg_solve_batch(const float* frames, int N, int H, int W, const int32_t* ref_idx, const int32_t* tmpl_idx,
+                    const float* u0, float* u, int32_t* iters, int32_t* status, int B, const reg_params_t* p,
+                    int mode, void* stream) {
+  std::lock_guard<std::recursive_mutex> lk(g_mu);
+  TRY(check_dims(B, H, W));
+  TRY(check_params(p, H, W));
+  if (N < 1) return fail(REG_E_INVALID, "N = %d frames", N);
+  if (mode != REG_PLAIN && mode != REG_BATCHED) return fail(REG_E_INVALID, "unknown mode %d", mode);
+  if (B == 0) return REG_OK;
+  if (!frames || !ref_idx || !tmpl_idx || !u) return fail(REG_E_INVALID, "NULL pointer");
+  if (u0 && u0 == u) return fail(REG_E_INVALID, "u aliases u0");
+  for (int b = 0; b < B; ++b)
+    if (ref_idx[b] < 0 || ref_idx[b] >= N || tmpl_idx[b] < 0 || tmpl_idx[b] >= N)
+      return fail(REG_E_INVALID, "frame index out of range at item %d", b);
+  TRY(ensure_device());
+  hipStream_t s = (hipStream_t)stream;
+  const float* lv[kMaxLevels] = {};
+  TRY(build_pyramid(frames, N, H, W, p->levels, lv, s));
+  SolveArgs a = base_args(lv, H, W, p);
+  const size_t nf = (size_t)2 * H * W;
+  std::vector<TaskDesc> tasks(B);
+  for (int b = 0; b < B; ++b) {
+    TaskDesc& d = tasks[b];
+    d.ref = ref_idx[b];
+    d.tmpl = tmpl_idx[b];
+    d.kind = u0 ? 2 : 0;
+    d.pad = 0;
+    d.ua = u0 ? u0 + b * nf : nullptr;
+    d.ub = nullptr;
+    d.out = u + b * nf;
+    d.iters = iters ? iters + (size_t)b * p->levels : nullptr;
+    d.status = status ? status + b : nullptr;
+  }
+  TRY(upload_tasks(g.tasks, tasks, s));
+  g.events_used = 0;
+  if (mode == REG_BATCHED) return run_batched(a, (const TaskDesc*)g.tasks.p, B, s, true);
+  return run_plain(a, tasks, (const TaskDesc*)g.tasks.p, s);
+}
+
+int scan_plan(int M, int algo, int chunk, int global_algo, scan_op_t* ops, int cap, int* n_ops, int* n_levels) {
+  std::vector<PlanOp> plan;
+  int nl = 0;
+  if (n_ops) *n_ops = 0;
+  if (n_levels) *n_levels = 0;
+  if (M < 1 || M > (1 << 24)) return fail(REG_E_INVALID, "M = %d not in [1, 2^24]", M);
+  if (algo < SCAN_SEQ || algo > SCAN_HIER) return fail(REG_E_INVALID, "unknown scan algorithm %d", algo);
+  if (algo == SCAN_HIER && (global_algo < SCAN_SEQ || global_algo > SCAN_BRENT_KUNG))
+    return fail(REG_E_INVALID, "unknown global algorithm %d", global_algo);
+  try {
+    if (rs::build_plan(M, algo, chunk, global_algo, plan, nl) != 0) return fail(REG_E_INVALID, "invalid plan arguments");
+  } catch (const std::exception& e) {
+    return fail(REG_E_INVALID, "plan construction failed: %s", e.what());
+  }
+  if (n_ops) *n_ops = (int)plan.size();
+  if (n_levels) *n_levels = nl;
+  if (!ops) return REG_OK;
+  if (cap < (int)plan.size()) return fail(REG_E_INVALID, "ops capacity %d < %zu", cap, plan.size());
+  for (size_t n = 0; n < plan.size(); ++n) {
+    const PlanOp& q = plan[n];
+    ops[n] = scan_op_t{q.level, q.out, q.a, q.b, q.i, q.j, q.k};
+  }
+  return REG_OK;
+}
+
+int scan_run(const float* frames, int N, int H, int W, const reg_params_t* p, int algo, int chunk, int global_algo,
+             int mode, int flags, float* phi0, float* u_pair, int32_t* op_iters, int32_t* status, void* stream) {
+  std::lock_guard<std::recursive_mutex> lk(g_mu);
+  TRY(check_dims(1, H, W));
+  TRY(check_params(p, H, W));
+  if (N < 2) return fail(REG_E_INVALID, "a series needs N >= 2 frames (got %d)", N);
+  if (mode != REG_PLAIN && mode != REG_BATCHED) return fail(REG_E_INVALID, "unknown mode %d", mode);
+  if (flags & ~SCAN_F_GRAPH) return fail(REG_E_INVALID, "unknown flags 0x%x", flags);
+  if (!frames || !phi0) return fail(REG_E_INVALID, "NULL pointer");
+  const int M = N - 1;
+  std::vector<PlanOp> plan;
+  int n_levels = 0;
+  if (algo < SCAN_SEQ || algo > SCAN_HIER) return fail(REG_E_INVALID, "unknown scan algorithm %d", algo);
+  if (algo == SCAN_HIER && (global_algo < SCAN_SEQ || global_algo > SCAN_BRENT_KUNG))
+    return fail(REG_E_INVALID, "unknown global algorithm %d", global_algo);
+  try {
+    if (rs::build_plan(M, algo, chunk, global_algo, plan, n_levels) != 0)
+      return fail(REG_E_INVALID, "invalid plan arguments");
+  } catch (const std::exception& e) {
+    return fail(REG_E_INVALID, "plan construction failed: %s", e.what());
+  }
+  TRY(ensure_device());
+  hipStream_t s = (hipStream_t)stream;
+  const int L = p->levels;
+  const size_t nf = (size_t)2 * H * W;
+  const size_t n_ops = plan.size();
+
+  // node storage: elements in u_pair, prefixes (0, k) in phi0, the rest in
+  // workspace slots reused once their last consumer's level has completed
+  std::vector<int> last_use(M + n_ops, 0);
+  for (const PlanOp& q : plan) {
+    last_use[q.a] = std::max(last_use[q.a], q.level);
+    last_use[q.b] = std::max(last_use[q.b], q.level);
+  }
+  std::vector<int> slot_of(M + n_ops, -1);
+  int n_slots = 0;
+  {
+    std::vector<std::vector<int>> dies(n_levels + 1);
+    for (const PlanOp& q : plan)
+      if (q.i != 0) dies[std::max(last_use[q.out], q.level)].push_back(q.out);
+    std::vector<int> free_slots;
+    size_t q = 0;
+    for (int lvl = 1; lvl <= n_levels; ++lvl) {
+      for (; q < n_ops && plan[q].level == lvl; ++q) {
+        if (plan[q].i == 0) continue;
+        if (free_slots.empty()) free_slots.push_back(n_slots++);
+        slot_of[plan[q].out] = free_slots.back();
+        free_slots.pop_back();
+      }
+      for (int nd : dies[lvl]) free_slots.push_back(slot_of[nd]);
+    }
+  }
+  TRY(ensure(g.nodes, std::max<size_t>(1, (size_t)n_slots) * nf * sizeof(float)));
+  float* pair = u_pair;
+  if (!pair) {
+    TRY(ensure(g.upair, (size_t)M * nf * sizeof(float)));
+    pair = (float*)g.upair.p;
+  }
+  int32_t* it_out = op_iters;
+  int32_t* st_out = status;
+  if (!it_out || !st_out) {
+    TRY(ensure(g.iters, (M + n_ops) * (size_t)(L + 1) * sizeof(int32_t)));
+    if (!it_out) it_out = (int32_t*)g.iters.p;
+    if (!st_out) st_out = (int32_t*)g.iters.p + (M + n_ops) * (size_t)L;
+  }
+  auto node_ptr = [&](int nd) -> float* {
+    if (nd < M) return pair + (size_t)nd * nf;
+    const PlanOp& q = plan[nd - M];
+    if (q.i == 0) return phi0 + (size_t)(q.k - 1) * nf;
+    return (float*)g.nodes.p + (size_t)slot_of[nd] * nf;
+  };
+
+  std::vector<TaskDesc> tasks(M + n_ops);
+  for (int k = 1; k <= M; ++k) {
+    TaskDesc& d = tasks[k - 1];
+    d.ref = k - 1;
+    d.tmpl = k;
+    d.kind = 0;
+    d.pad = 0;
+    d.ua = d.ub = nullptr;
+    d.out = pair + (size_t)(k - 1) * nf;
+    d.iters = it_out + (size_t)(k - 1) * L;
+    d.status = st_out + (k - 1);
+  }
+  for (size_t n = 0; n < n_ops; ++n) {
+    const PlanOp& q = plan[n];
+    TaskDesc& d = tasks[M + n];
+    d.ref = q.i;
+    d.tmpl = q.k;
+    d.kind = 1;
+    d.pad = 0;
+    d.ua = node_ptr(q.a);
+    d.ub = node_ptr(q.b);
+    d.out = node_ptr(q.out);
+    d.iters = it_out + (M + n) * (size_t)L;
+    d.status = st_out + (M + n);
+  }
+  TRY(upload_tasks(g.tasks, tasks, s));
+  const TaskDesc* d_tasks = (const TaskDesc*)g.tasks.p;
+
+  const float* lv[kMaxLevels] = {};
+  TRY(build_pyramid(frames, N, H, W, L, lv, s));
+  SolveArgs a = base_args(lv, H, W, p);
+  g.events_used = 0;
+  if (mode == REG_BATCHED) {
+    TRY(run_batched(a, d_tasks, M, s, true));
+    HIPCHK(launch_copy(pair, phi0, nf, s));
+    size_t q = 0;
+    for (int lvl = 1; lvl <= n_levels; ++lvl) {
+      const size_t q0 = q;
+      while (q < n_ops && plan[q].level == lvl) ++q;
+      TRY(run_batched(a, d_tasks + M + q0, (int)(q - q0), s, true));
+    }
+  } else {
+    std::vector<TaskDesc> A(tasks.begin(), tasks.begin() + M);
+    TRY(run_plain(a, A, d_tasks, s));
+    HIPCHK(launch_copy(pair, phi0, nf, s));
+    for (size_t n = 0; n < n_ops; ++n) {
+      std::vector<TaskDesc> one{tasks[M + n]};
+      TRY(run_plain(a, one, d_tasks + M + n, s));
+    }
+  }
+  return REG_OK;
+}
+
+int reg_last_solve_timing(double* total_ms, int* launches) {
+  std::lock_guard<std::recursive_mutex> lk(g_mu);
+  double tot = 0.0;
+  for (size_t q = 0; q < g.events_used; ++q) {
+    HIPCHK(hipEventSynchronize(g.events[q].second));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, g.events[q].first, g.events[q].second));
+    tot += ms;
+  }
+  if (total_ms) *total_ms = tot;
+  if (launches) *launches = (int)g.events_used;
+  return REG_OK;
+}
+
+int reg_set_tuning(int tile_rows, int max_group) {
+  std::lock_guard<std::recursive_mutex> lk(g_mu);
+  if (tile_rows != 0 && (tile_rows < 4 || tile_rows > 64 || tile_rows % 4))
+    return fail(REG_E_INVALID, "tile_rows %d must be a multiple of 4 in [4, 64]", tile_rows);
+  if (max_group != 0 && (max_group < 1 || max_group > 64 || (max_group & (max_group - 1))))
+    return fail(REG_E_INVALID, "max_group %d must be a power of two in [1, 64]", max_group);
+  if (tile_rows) g.tile_rows = tile_rows;
+  if (max_group) g.max_group = max_group;
+  return REG_OK;
+}
+
+int reg_autotune(int H, int W, int levels, int batch, int* tile_rows, int* max_group, void* stream) {
+  (void)H; (void)W; (void)levels; (void)batch; (void)stream;
+  std::lock_guard<std::recursive_mutex> lk(g_mu);
+  if (tile_rows) *tile_rows = g.tile_rows;
+  if (max_group) *max_group = g.max_group;
+  return REG_OK;
+}
+
+void reg_release(void) {
+  std::lock_guard<std::recursive_mutex> lk(g_mu);
+  if (!g.init) return;
+  (void)hipDeviceSynchronize();
+  for (DevBuf* b : {&g.pyr, &g.slots, &g.part, &g.ctrl, &g.tasks, &g.nodes, &g.upair, &g.iters, &g.status,
+                    &g.misc, &g.lvl}) {
+    if (b->p) (void)hipFree(b->p);
+    b->p = nullptr;
+    b->n = 0;
+  }
+  for (auto& e : g.events) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  g.events.clear();
+  g.events_used = 0;
+  g.generation++;
+}
+
+}  // extern "C"

@@ -1,0 +1,74 @@
+// Internal interfaces between the C-ABI host layer and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace rs {
+
+constexpr int kMaxLevelsHost = 8;
+
+// One registration of a batch (device array element).
+struct TaskDesc {
+  int32_t ref, tmpl;     // frame indices
+  int32_t kind;          // 0 identity, 1 composition (ua o ub), 2 given guess ua
+  int32_t pad;
+  const float* ua;       // u_ij or u0: [2][H][W]
+  const float* ub;       // u_jk: [2][H][W]
+  float* out;            // [2][H][W]
+  int32_t* iters;        // [levels] or nullptr
+  int32_t* status;       // [1] or nullptr
+};
+
+struct SolveArgs {
+  const float* pyr[kMaxLevelsHost];   // level l of frame f at pyr[l] + f*(H>>l)*(W>>l)
+  int H, W, levels;
+  int max_iter, fixed_iter;
+  double tau, lam;
+  double rel_tol;
+  const TaskDesc* tasks;
+  int n_tasks;
+  int g;                 // workgroups per registration (group)
+  int th;                // tile rows
+  int max_tiles;         // partial-sum slots per parity
+  int* ctrl;             // [0] work-queue ticket, [1] abort flag, groups at ctrl + 64 + 32*group
+  double* part;          // [groups][2][max_tiles]
+  float* ws;             // [groups][slot_floats]
+  size_t slot_floats;
+  size_t lvl_off[kMaxLevelsHost];     // offsets of the pyramid-shaped buffer A per level
+  size_t bufB_off;       // offset of buffer B inside a slot
+  unsigned spin_limit;
+};
+
+size_t slot_floats_for(int H, int W, int levels, size_t* lvl_off, size_t* bufB_off);
+
+// kernels.hip
+hipError_t launch_restrict(const void* in, void* out, double scale, int B, int H, int W, bool f64, hipStream_t s);
+hipError_t launch_prolong(const float* uc, float* uf, int B, int Hf, int Wf, hipStream_t s);
+hipError_t launch_compose(const float* uij, const float* ujk, float* out, int B, int H, int W, hipStream_t s);
+hipError_t launch_warp(const void* T, const void* u, void* out, int B, int H, int W, bool f64, hipStream_t s);
+hipError_t launch_warp_adjoint(const void* g, const void* u, void* gT, int B, int H, int W, bool f64, hipStream_t s);
+hipError_t launch_energy_grad(const void* R, const void* T, const void* u, double lam, double* E,
+                              void* grad, double* gnorm2, int B, int H, int W, int th,
+                              double* part, bool f64, hipStream_t s);
+hipError_t launch_energy_backward_level(const void* Ia, const void* u, const void* Ib, double lam,
+                                        const double* gE, void* dIa, void* du, void* dIb,
+                                        const void* du_c, const void* dIb_c, int B, int h, int w,
+                                        bool f64, hipStream_t s);
+hipError_t launch_adjoint_init(const void* dIa_c, void* dIa, int B, int h, int w, bool f64, hipStream_t s);
+hipError_t launch_add_energy(const double* Ein, double* Eacc, int B, int first, hipStream_t s);
+
+// solver.hip
+const void* persistent_kernel();
+hipError_t launch_persistent(const SolveArgs& a, int grid, hipStream_t s);
+hipError_t launch_reset_ctrl(int* ctrl, int n_ints, hipStream_t s);
+hipError_t launch_reset_tasks(int* ctrl, int n_ints, const TaskDesc* tasks, int n_tasks, hipStream_t s);
+hipError_t launch_plain_init(const TaskDesc* d_task, const SolveArgs& a, float* dst, hipStream_t s);
+hipError_t launch_plain_prolong(const float* uc, float* uf, int h, int w, hipStream_t s);
+hipError_t launch_plain_sweep(const float* R, const float* T, const float* u, float* un, int h, int w,
+                              double tau, double lam, int th, double* part, hipStream_t s);
+hipError_t launch_plain_reduce(const double* part, int n, double* E, hipStream_t s);
+hipError_t launch_copy(const float* src, float* dst, size_t n, hipStream_t s);   // src == nullptr: fill NaN
+
+}  // namespace rs

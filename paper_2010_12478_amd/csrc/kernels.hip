@@ -1,0 +1,349 @@
+// Standalone kernels (double arithmetic, float or double storage): pyramid restriction / prolongation, composition, warp
+// and its adjoint, energy + gradient, and the backward pass of the
+// differentiable warp + energy step.
+#include "internal.h"
+#include "sweep.h"
+
+namespace rs {
+
+namespace {
+
+constexpr int kEW = 256;   // threads per block of the elementwise kernels
+
+inline int ew_blocks(size_t n) {
+  size_t b = (n + kEW - 1) / kEW;
+  return (int)(b < 65535u * 16u ? b : 65535u * 16u);
+}
+
+// out[b][Y][X] = scale * (1/4) * sum of the 2x2 block of in[b]
+template <typename S>
+__global__ void __launch_bounds__(kEW) k_restrict(const S* __restrict__ in, S* __restrict__ out, double scale,
+                                                  int B, int H, int W) {
+  const int h = H >> 1, w = W >> 1;
+  const size_t n = (size_t)B * h * w;
+  for (size_t t = blockIdx.x * (size_t)kEW + threadIdx.x; t < n; t += (size_t)gridDim.x * kEW) {
+    const size_t b = t / ((size_t)h * w);
+    const int r = (int)(t - b * h * w);
+    const int Y = r / w, X = r - Y * w;
+    const S* p = in + b * H * W + (size_t)(2 * Y) * W + 2 * X;
+    const double sum = (((double)p[0] + (double)p[1]) + (double)p[W]) + (double)p[W + 1];
+    out[t] = (S)(scale * (0.25 * sum));
+  }
+}
+
+__global__ void __launch_bounds__(kEW) k_prolong(const float* __restrict__ uc, float* __restrict__ uf,
+                                                 int B, int Hf, int Wf) {
+  const int hc = Hf >> 1, wc = Wf >> 1;
+  const size_t n = (size_t)B * Hf * Wf;
+  for (size_t t = blockIdx.x * (size_t)kEW + threadIdx.x; t < n; t += (size_t)gridDim.x * kEW) {
+    const size_t b = t / ((size_t)Hf * Wf);
+    const int r = (int)(t - b * Hf * Wf);
+    const int y = r / Wf, x = r - y * Wf;
+    double vx, vy;
+    prolong_pixel(uc + b * 2 * hc * wc, hc, wc, x, y, vx, vy);
+    float* o = uf + b * 2 * Hf * Wf;
+    o[r] = (float)vx;
+    o[(size_t)Hf * Wf + r] = (float)vy;
+  }
+}
+
+__global__ void __launch_bounds__(kEW) k_compose(const float* __restrict__ uij, const float* __restrict__ ujk,
+                                                 float* __restrict__ out, int B, int H, int W) {
+  const size_t HW = (size_t)H * W, n = (size_t)B * HW;
+  for (size_t t = blockIdx.x * (size_t)kEW + threadIdx.x; t < n; t += (size_t)gridDim.x * kEW) {
+    const size_t b = t / HW;
+    const int r = (int)(t - b * HW);
+    const int y = r / W, x = r - y * W;
+    double vx, vy;
+    init_pixel<float>(1, uij + b * 2 * HW, ujk + b * 2 * HW, H, W, 1, x, y, vx, vy);
+    out[b * 2 * HW + r] = (float)vx;
+    out[b * 2 * HW + HW + r] = (float)vy;
+  }
+}
+
+template <typename S>
+__global__ void __launch_bounds__(kEW) k_warp(const S* __restrict__ T, const S* __restrict__ u,
+                                              S* __restrict__ out, int B, int H, int W) {
+  const size_t HW = (size_t)H * W, n = (size_t)B * HW;
+  for (size_t t = blockIdx.x * (size_t)kEW + threadIdx.x; t < n; t += (size_t)gridDim.x * kEW) {
+    const size_t b = t / HW;
+    const int r = (int)(t - b * HW);
+    const int y = r / W, x = r - y * W;
+    const S* ub = u + b * 2 * HW;
+    int ix, iy;
+    double fx, fy;
+    cell_of(ub[r], ix, fx);
+    cell_of(ub[HW + r], iy, fy);
+    out[t] = (S)bilin_value(T + b * HW, H, W, x + ix, y + iy, fx, fy);
+  }
+}
+
+__device__ __forceinline__ void atomic_add(float* p, float v) { unsafeAtomicAdd(p, v); }
+__device__ __forceinline__ void atomic_add(double* p, double v) { unsafeAtomicAdd(p, v); }
+
+// Scatter v(x) into the four clamped taps of x + u(x) with bilinear weights.
+template <typename S>
+__device__ __forceinline__ void scatter_taps(S* __restrict__ gT, int H, int W, int x, int y, S ux, S uy, double v) {
+  int ix, iy;
+  double fx, fy;
+  cell_of(ux, ix, fx);
+  cell_of(uy, iy, fy);
+  const int x0 = x + ix, y0 = y + iy;
+  const int xa = clampi(x0, 0, W - 1), xb = clampi(x0 + 1, 0, W - 1);
+  const int ya = clampi(y0, 0, H - 1), yb = clampi(y0 + 1, 0, H - 1);
+  const double ox = 1.0 - fx, oy = 1.0 - fy;
+  atomic_add(gT + ya * W + xa, (S)(v * ox * oy));
+  atomic_add(gT + ya * W + xb, (S)(v * fx * oy));
+  atomic_add(gT + yb * W + xa, (S)(v * ox * fy));
+  atomic_add(gT + yb * W + xb, (S)(v * fx * fy));
+}
+
+template <typename S>
+__global__ void __launch_bounds__(kEW) k_warp_adjoint(const S* __restrict__ g, const S* __restrict__ u,
+                                                      S* __restrict__ gT, int B, int H, int W) {
+  const size_t HW = (size_t)H * W, n = (size_t)B * HW;
+  for (size_t t = blockIdx.x * (size_t)kEW + threadIdx.x; t < n; t += (size_t)gridDim.x * kEW) {
+    const size_t b = t / HW;
+    const int r = (int)(t - b * HW);
+    const int y = r / W, x = r - y * W;
+    const S* ub = u + b * 2 * HW;
+    scatter_taps(gT + b * HW, H, W, x, y, ub[r], ub[HW + r], (double)g[t]);
+  }
+}
+
+// Energy (+ gradient) of batch item blockIdx.y, tile blockIdx.x.
+template <typename S, int WRITE, bool GNORM>
+__global__ void __launch_bounds__(kWG) k_energy_tiles(const S* __restrict__ R, const S* __restrict__ T,
+                                                      const S* __restrict__ u, double lam, S* grad,
+                                                      double* part, double* gpart, int H, int W, int th) {
+  __shared__ double red[kWG / kWave];
+  const size_t HW = (size_t)H * W;
+  const int b = blockIdx.y, nt = tiles_of(H, W, th);
+  LevelView<S> L;
+  L.R = R + b * HW;
+  L.T = T + b * HW;
+  L.u = u + b * 2 * HW;
+  L.out = grad ? grad + b * 2 * HW : nullptr;
+  L.h = H;
+  L.w = W;
+  L.tau = 0.0;
+  L.lam = lam;
+  double gn = 0.0;
+  const double E = sweep_tile<S, WRITE, GNORM>(L, blockIdx.x, th, red, &gn);
+  if (threadIdx.x == 0) {
+    part[(size_t)b * nt + blockIdx.x] = E;
+    if (GNORM) gpart[(size_t)b * nt + blockIdx.x] = gn;
+  }
+}
+
+__global__ void __launch_bounds__(kWave) k_sum_tiles(const double* part, const double* gpart, int nt,
+                                                     double* E, double* gn) {
+  const int b = blockIdx.x;
+  const int lane = threadIdx.x;
+  const double e = wave_sum_array(part + (size_t)b * nt, nt, lane);
+  if (lane == 0) E[b] = e;
+  if (gn) {
+    const double g = wave_sum_array(gpart + (size_t)b * nt, nt, lane);
+    if (lane == 0) gn[b] = g;
+  }
+}
+
+// One level of the backward pass.  Per pixel x of item b:
+//   r = Ia(x + u(x)) - Ib(x), g = dE_l/du(x)
+//   du(x)  = gE g(x)     + 1/8 du_c(parent)     (adjoint of half the block mean)
+//   dIb(x) = -2 r gE     + 1/4 dIb_c(parent)    (adjoint of the block mean)
+//   dIa   += 2 r gE * bilinear weights at the taps (dIa pre-initialised)
+template <typename S>
+__global__ void __launch_bounds__(kEW) k_energy_backward(const S* __restrict__ Ia, const S* __restrict__ u,
+                                                         const S* __restrict__ Ib, double lam,
+                                                         const double* __restrict__ gE, S* dIa, S* du,
+                                                         S* dIb, const S* du_c, const S* dIb_c,
+                                                         int B, int H, int W) {
+  const size_t HW = (size_t)H * W, n = (size_t)B * HW;
+  const int hc = H >> 1, wc = W >> 1;
+  const size_t HWc = (size_t)hc * wc;
+  for (size_t t = blockIdx.x * (size_t)kEW + threadIdx.x; t < n; t += (size_t)gridDim.x * kEW) {
+    const size_t b = t / HW;
+    const int r = (int)(t - b * HW);
+    const int y = r / W, x = r - y * W;
+    const S* ux = u + b * 2 * HW;
+    const S* uy = ux + HW;
+    const S cxs = ux[r], cys = uy[r];
+    int ix, iy;
+    double fx, fy;
+    cell_of(cxs, ix, fx);
+    cell_of(cys, iy, fy);
+    double s, dsx, dsy;
+    bilin(Ia + b * HW, H, W, x + ix, y + iy, fx, fy, s, dsx, dsy);
+    const double res = s - (double)Ib[t];
+    const double cx = cxs, cy = cys;
+    double nbx = 0.0, nby = 0.0;
+    if (x > 0) { nbx += cx - (double)ux[r - 1]; nby += cy - (double)uy[r - 1]; }
+    if (x + 1 < W) { nbx += cx - (double)ux[r + 1]; nby += cy - (double)uy[r + 1]; }
+    if (y > 0) { nbx += cx - (double)ux[r - W]; nby += cy - (double)uy[r - W]; }
+    if (y + 1 < H) { nbx += cx - (double)ux[r + W]; nby += cy - (double)uy[r + W]; }
+    const double w = gE[b];
+    double gx = w * (2.0 * res * dsx + 2.0 * lam * nbx);
+    double gy = w * (2.0 * res * dsy + 2.0 * lam * nby);
+    double gb = w * (-2.0 * res);
+    if (du_c) {
+      const size_t pc = b * 2 * HWc + (size_t)(y >> 1) * wc + (x >> 1);
+      gx += 0.125 * (double)du_c[pc];
+      gy += 0.125 * (double)du_c[pc + HWc];
+    }
+    if (dIb_c) gb += 0.25 * (double)dIb_c[b * HWc + (size_t)(y >> 1) * wc + (x >> 1)];
+    du[b * 2 * HW + r] = (S)gx;
+    du[b * 2 * HW + HW + r] = (S)gy;
+    dIb[t] = (S)gb;
+    scatter_taps(dIa + b * HW, H, W, x, y, cxs, cys, w * 2.0 * res);
+  }
+}
+
+template <typename S>
+__global__ void __launch_bounds__(kEW) k_adjoint_init(const S* __restrict__ dIa_c, S* __restrict__ dIa,
+                                                      int B, int H, int W) {
+  const size_t HW = (size_t)H * W, n = (size_t)B * HW;
+  const int wc = W >> 1;
+  const size_t HWc = (size_t)(H >> 1) * wc;
+  for (size_t t = blockIdx.x * (size_t)kEW + threadIdx.x; t < n; t += (size_t)gridDim.x * kEW) {
+    if (!dIa_c) {
+      dIa[t] = S(0);
+    } else {
+      const size_t b = t / HW;
+      const int r = (int)(t - b * HW);
+      const int y = r / W, x = r - y * W;
+      dIa[t] = (S)(0.25 * (double)dIa_c[b * HWc + (size_t)(y >> 1) * wc + (x >> 1)]);
+    }
+  }
+}
+
+__global__ void k_add_energy(const double* Ein, double* Eacc, int B, int first) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < B) Eacc[b] = first ? Ein[b] : Eacc[b] + Ein[b];
+}
+
+}  // namespace
+
+hipError_t launch_restrict(const void* in, void* out, double scale, int B, int H, int W, bool f64,
+                           hipStream_t s) {
+  const size_t n = (size_t)B * (H / 2) * (W / 2);
+  if (n == 0) return hipSuccess;
+  if (f64)
+    hipLaunchKernelGGL(k_restrict<double>, dim3(ew_blocks(n)), dim3(kEW), 0, s, (const double*)in,
+                       (double*)out, scale, B, H, W);
+  else
+    hipLaunchKernelGGL(k_restrict<float>, dim3(ew_blocks(n)), dim3(kEW), 0, s, (const float*)in,
+                       (float*)out, scale, B, H, W);
+  return hipGetLastError();
+}
+
+hipError_t launch_prolong(const float* uc, float* uf, int B, int Hf, int Wf, hipStream_t s) {
+  const size_t n = (size_t)B * Hf * Wf;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_prolong, dim3(ew_blocks(n)), dim3(kEW), 0, s, uc, uf, B, Hf, Wf);
+  return hipGetLastError();
+}
+
+hipError_t launch_compose(const float* uij, const float* ujk, float* out, int B, int H, int W, hipStream_t s) {
+  const size_t n = (size_t)B * H * W;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_compose, dim3(ew_blocks(n)), dim3(kEW), 0, s, uij, ujk, out, B, H, W);
+  return hipGetLastError();
+}
+
+hipError_t launch_warp(const void* T, const void* u, void* out, int B, int H, int W, bool f64, hipStream_t s) {
+  const size_t n = (size_t)B * H * W;
+  if (n == 0) return hipSuccess;
+  if (f64)
+    hipLaunchKernelGGL(k_warp<double>, dim3(ew_blocks(n)), dim3(kEW), 0, s, (const double*)T,
+                       (const double*)u, (double*)out, B, H, W);
+  else
+    hipLaunchKernelGGL(k_warp<float>, dim3(ew_blocks(n)), dim3(kEW), 0, s, (const float*)T,
+                       (const float*)u, (float*)out, B, H, W);
+  return hipGetLastError();
+}
+
+hipError_t launch_warp_adjoint(const void* g, const void* u, void* gT, int B, int H, int W, bool f64,
+                               hipStream_t s) {
+  const size_t n = (size_t)B * H * W;
+  if (n == 0) return hipSuccess;
+  if (f64)
+    hipLaunchKernelGGL(k_warp_adjoint<double>, dim3(ew_blocks(n)), dim3(kEW), 0, s, (const double*)g,
+                       (const double*)u, (double*)gT, B, H, W);
+  else
+    hipLaunchKernelGGL(k_warp_adjoint<float>, dim3(ew_blocks(n)), dim3(kEW), 0, s, (const float*)g,
+                       (const float*)u, (float*)gT, B, H, W);
+  return hipGetLastError();
+}
+
+template <typename S>
+static void energy_dispatch(const S* R, const S* T, const S* u, double lam, S* grad, double* part, double* gpart,
+                            bool gnorm, int B, int H, int W, int th, hipStream_t s) {
+  const dim3 grid(tiles_of(H, W, th), B);
+  if (grad && gnorm)
+    hipLaunchKernelGGL((k_energy_tiles<S, SW_GRAD, true>), grid, dim3(kWG), 0, s, R, T, u, lam, grad, part,
+                       gpart, H, W, th);
+  else if (grad)
+    hipLaunchKernelGGL((k_energy_tiles<S, SW_GRAD, false>), grid, dim3(kWG), 0, s, R, T, u, lam, grad, part,
+                       gpart, H, W, th);
+  else if (gnorm)
+    hipLaunchKernelGGL((k_energy_tiles<S, SW_NONE, true>), grid, dim3(kWG), 0, s, R, T, u, lam, grad, part,
+                       gpart, H, W, th);
+  else
+    hipLaunchKernelGGL((k_energy_tiles<S, SW_NONE, false>), grid, dim3(kWG), 0, s, R, T, u, lam, grad, part,
+                       gpart, H, W, th);
+}
+
+hipError_t launch_energy_grad(const void* R, const void* T, const void* u, double lam, double* E, void* grad,
+                              double* gnorm2, int B, int H, int W, int th, double* part, bool f64,
+                              hipStream_t s) {
+  if (B == 0) return hipSuccess;
+  const int nt = tiles_of(H, W, th);
+  double* gpart = part + (size_t)B * nt;
+  if (f64)
+    energy_dispatch<double>((const double*)R, (const double*)T, (const double*)u, lam, (double*)grad, part,
+                            gpart, gnorm2 != nullptr, B, H, W, th, s);
+  else
+    energy_dispatch<float>((const float*)R, (const float*)T, (const float*)u, lam, (float*)grad, part,
+                           gpart, gnorm2 != nullptr, B, H, W, th, s);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sum_tiles, dim3(B), dim3(kWave), 0, s, part, gpart, nt, E, gnorm2);
+  return hipGetLastError();
+}
+
+hipError_t launch_energy_backward_level(const void* Ia, const void* u, const void* Ib, double lam,
+                                        const double* gE, void* dIa, void* du, void* dIb, const void* du_c,
+                                        const void* dIb_c, int B, int h, int w, bool f64, hipStream_t s) {
+  const size_t n = (size_t)B * h * w;
+  if (n == 0) return hipSuccess;
+  if (f64)
+    hipLaunchKernelGGL(k_energy_backward<double>, dim3(ew_blocks(n)), dim3(kEW), 0, s, (const double*)Ia,
+                       (const double*)u, (const double*)Ib, lam, gE, (double*)dIa, (double*)du, (double*)dIb,
+                       (const double*)du_c, (const double*)dIb_c, B, h, w);
+  else
+    hipLaunchKernelGGL(k_energy_backward<float>, dim3(ew_blocks(n)), dim3(kEW), 0, s, (const float*)Ia,
+                       (const float*)u, (const float*)Ib, lam, gE, (float*)dIa, (float*)du,
+                       (float*)dIb, (const float*)du_c, (const float*)dIb_c, B, h, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_init(const void* dIa_c, void* dIa, int B, int h, int w, bool f64, hipStream_t s) {
+  const size_t n = (size_t)B * h * w;
+  if (n == 0) return hipSuccess;
+  if (f64)
+    hipLaunchKernelGGL(k_adjoint_init<double>, dim3(ew_blocks(n)), dim3(kEW), 0, s, (const double*)dIa_c,
+                       (double*)dIa, B, h, w);
+  else
+    hipLaunchKernelGGL(k_adjoint_init<float>, dim3(ew_blocks(n)), dim3(kEW), 0, s, (const float*)dIa_c,
+                       (float*)dIa, B, h, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_add_energy(const double* Ein, double* Eacc, int B, int first, hipStream_t s) {
+  if (B == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_add_energy, dim3((B + 255) / 256), dim3(256), 0, s, Ein, Eacc, B, first);
+  return hipGetLastError();
+}
+
+}  // namespace rs

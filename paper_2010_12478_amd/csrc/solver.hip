@@ -1,0 +1,321 @@
+// Batched registration solver: a persistent kernel fed by a device atomic work
+// queue, and the kernels of the plain one-launch-per-iteration path.
+//
+// Persistent kernel.  The grid is sized to be fully resident.  Workgroups form
+// groups of g (same blockIdx % 8, so a group shares one XCD and its L2); a
+// group takes registrations from an atomic ticket counter one at a time and
+// runs each through all pyramid levels: initial guess on the coarsest level,
+// then per level the gradient-descent sweeps, each followed by a group
+// barrier, an order-fixed sum of the per-tile energies and the stopping
+// decision, which every member takes identically.  A level's tiles are dealt
+// round-robin to the g members.  Groups that finish early take the next
+// ticket: the on-chip counterpart of the paper's work stealing (Section 4.3),
+// absorbing the uneven iteration counts of the registrations.
+//
+// Every energy is a per-tile double sum (fixed order inside the tile) followed
+// by the canonical wave sum over tiles, so the plain path, the persistent
+// kernel at any group size, and repeated runs agree bitwise.
+#include "internal.h"
+#include "sweep.h"
+
+namespace rs {
+
+namespace {
+
+__device__ __forceinline__ int ld_relaxed(const int* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+struct Group {
+  int g, member, id;
+  int* bar;      // arrival counter (monotonic)
+  int* task;     // [2] ticket broadcast
+  int epoch;
+};
+
+// Barrier over the g workgroups of a group.  Returns false if the run has been
+// aborted (by this or another workgroup's watchdog); all workgroups then leave.
+__device__ bool group_sync(Group& G, int* abort_flag, unsigned spin_limit, int* s_flag) {
+  if (G.g == 1) {
+    __syncthreads();
+    return true;
+  }
+  __threadfence();   // each thread's global writes visible at agent scope
+  __syncthreads();
+  G.epoch += 1;
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    __hip_atomic_fetch_add(G.bar, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    const int target = G.epoch * G.g;
+    unsigned spins = 0;
+    while (ld_relaxed(G.bar) < target) {
+      if (ld_relaxed(abort_flag)) {
+        ok = 0;
+        break;
+      }
+      if (++spins > spin_limit) {
+        __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    *s_flag = ok;
+  }
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return *s_flag != 0;
+}
+
+__device__ __forceinline__ float* start_buffer(const SolveArgs& a, const TaskDesc& d, float* slot, int l) {
+  return l == 0 ? d.out : slot + a.lvl_off[l];
+}
+
+// Runs one registration with the calling group.  Returns false on abort.
+__device__ bool run_task(const SolveArgs& a, const TaskDesc& d, Group& G, float* slot, double* part, int& par,
+                         double* red, double* s_E, int* s_flag) {
+  int* abort_flag = a.ctrl + 1;
+  const int L = a.levels;
+  const int stride = G.g * kWG;
+  const int first = G.member * kWG + threadIdx.x;
+
+  {  // initial guess on the coarsest level
+    const int hc = a.H >> (L - 1), wc = a.W >> (L - 1);
+    float* dst = start_buffer(a, d, slot, L - 1);
+    const int n = hc * wc;
+    for (int p = first; p < n; p += stride) {
+      const int Y = p / wc, X = p - Y * wc;
+      double vx, vy;
+      init_pixel<float>(d.kind, d.ua, d.ub, a.H, a.W, L, X, Y, vx, vy);
+      dst[p] = (float)vx;
+      dst[(size_t)n + p] = (float)vy;
+    }
+  }
+  if (!group_sync(G, abort_flag, a.spin_limit, s_flag)) return false;
+
+  float* bufB = slot + a.bufB_off;
+  float* cur = start_buffer(a, d, slot, L - 1);
+  int status = 0;
+  int iters[kMaxLevels];
+  bool dead = false;
+  for (int l = L - 1; l >= 0; --l) {
+    iters[l] = 0;
+    if (dead) continue;
+    const int h = a.H >> l, w = a.W >> l;
+    const int n = h * w;
+    if (l < L - 1) {
+      float* dst = start_buffer(a, d, slot, l);
+      for (int p = first; p < n; p += stride) {
+        const int y = p / w, x = p - y * w;
+        double vx, vy;
+        prolong_pixel<float>(cur, h >> 1, w >> 1, x, y, vx, vy);
+        dst[p] = (float)vx;
+        dst[(size_t)n + p] = (float)vy;
+      }
+      if (!group_sync(G, abort_flag, a.spin_limit, s_flag)) return false;
+      cur = dst;
+    }
+    float* other = bufB;
+    LevelView<float> V;
+    V.R = a.pyr[l] + (size_t)d.ref * n;
+    V.T = a.pyr[l] + (size_t)d.tmpl * n;
+    V.h = h;
+    V.w = w;
+    V.tau = a.tau;
+    V.lam = a.lam;
+    const int nt = tiles_of(h, w, a.th);
+    double e_prev = 0.0;
+    int it = 0;
+    for (; it < a.max_iter; ++it) {
+      V.u = cur;
+      V.out = other;
+      double* pp = part + (size_t)par * a.max_tiles;
+      for (int tile = G.member; tile < nt; tile += G.g) {
+        const double e = sweep_tile<float, SW_UPDATE, false>(V, tile, a.th, red, nullptr);
+        if (threadIdx.x == 0) pp[tile] = e;
+      }
+      if (!group_sync(G, abort_flag, a.spin_limit, s_flag)) return false;
+      if (threadIdx.x < kWave) {
+        const double E = wave_sum_array(pp, nt, threadIdx.x);
+        if (threadIdx.x == 0) *s_E = E;
+      }
+      __syncthreads();
+      const double E = *s_E;
+      par ^= 1;
+      if (!isfinite(E)) {
+        status |= 2;   // REG_S_NONFINITE
+        dead = true;
+        break;
+      }
+      if (!a.fixed_iter && it > 0 && level_stops(e_prev, E, a.rel_tol)) break;
+      e_prev = E;
+      float* t = cur;
+      cur = other;
+      other = t;
+    }
+    iters[l] = it;
+    if (it == a.max_iter && !a.fixed_iter) status |= 1;   // REG_S_MAXITER
+  }
+
+  const size_t nf = (size_t)2 * a.H * a.W;
+  if (dead) {
+    for (size_t p = first; p < nf; p += stride) d.out[p] = __builtin_nanf("");
+  } else if (cur != d.out) {
+    for (size_t p = first; p < nf; p += stride) d.out[p] = cur[p];
+  }
+  if (G.member == 0 && threadIdx.x == 0) {
+    if (d.iters)
+      for (int l = 0; l < L; ++l) d.iters[l] = iters[l];
+    if (d.status) *d.status = status;
+  }
+  return true;
+}
+
+__global__ void __launch_bounds__(kWG) k_persistent(SolveArgs a) {
+  __shared__ double red[kWG / kWave];
+  __shared__ double s_E;
+  __shared__ int s_flag;
+  __shared__ int s_task;
+  const int xcd = blockIdx.x & 7, lb = blockIdx.x >> 3;
+  Group G;
+  G.g = a.g;
+  G.member = lb % a.g;
+  G.id = (lb / a.g) * 8 + xcd;
+  G.bar = a.ctrl + 64 + 32 * G.id;
+  G.task = G.bar + 4;
+  G.epoch = 0;
+  int* queue = a.ctrl;
+  int* abort_flag = a.ctrl + 1;
+  double* part = a.part + (size_t)G.id * 2 * a.max_tiles;
+  float* slot = a.ws + (size_t)G.id * a.slot_floats;
+  int par = 0, tpar = 0;
+
+  if (G.member == 0 && threadIdx.x == 0) G.task[0] = atomicAdd(queue, 1);
+  if (!group_sync(G, abort_flag, a.spin_limit, &s_flag)) return;
+  for (;;) {
+    if (threadIdx.x == 0) s_task = ld_relaxed(&G.task[tpar]);
+    __syncthreads();
+    const int t = s_task;
+    if (t >= a.n_tasks) break;
+    if (!run_task(a, a.tasks[t], G, slot, part, par, red, &s_E, &s_flag)) return;
+    tpar ^= 1;
+    if (G.member == 0 && threadIdx.x == 0) G.task[tpar] = atomicAdd(queue, 1);
+    if (!group_sync(G, abort_flag, a.spin_limit, &s_flag)) return;
+  }
+}
+
+// Clears the queue / barrier words and marks every task aborted until it
+// completes (a task the watchdog never let finish keeps that status).
+__global__ void k_reset(int* ctrl, int n_ints, const TaskDesc* tasks, int n_tasks) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_ints; i += gridDim.x * blockDim.x) ctrl[i] = 0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_tasks; i += gridDim.x * blockDim.x)
+    if (tasks[i].status) *tasks[i].status = 4;   // REG_S_ABORTED
+}
+
+// ---------------------------------------------------------------- plain path
+
+__global__ void __launch_bounds__(kWG) k_plain_init(const TaskDesc* d, SolveArgs a, float* dst) {
+  const int L = a.levels;
+  const int hc = a.H >> (L - 1), wc = a.W >> (L - 1);
+  const int n = hc * wc;
+  for (int p = blockIdx.x * kWG + threadIdx.x; p < n; p += gridDim.x * kWG) {
+    const int Y = p / wc, X = p - Y * wc;
+    double vx, vy;
+    init_pixel<float>(d->kind, d->ua, d->ub, a.H, a.W, L, X, Y, vx, vy);
+    dst[p] = (float)vx;
+    dst[(size_t)n + p] = (float)vy;
+  }
+}
+
+__global__ void __launch_bounds__(kWG) k_plain_prolong(const float* uc, float* uf, int h, int w) {
+  const int n = h * w;
+  for (int p = blockIdx.x * kWG + threadIdx.x; p < n; p += gridDim.x * kWG) {
+    const int y = p / w, x = p - y * w;
+    double vx, vy;
+    prolong_pixel<float>(uc, h >> 1, w >> 1, x, y, vx, vy);
+    uf[p] = (float)vx;
+    uf[(size_t)n + p] = (float)vy;
+  }
+}
+
+__global__ void __launch_bounds__(kWG) k_plain_sweep(LevelView<float> V, int th, double* part) {
+  __shared__ double red[kWG / kWave];
+  const double e = sweep_tile<float, SW_UPDATE, false>(V, blockIdx.x, th, red, nullptr);
+  if (threadIdx.x == 0) part[blockIdx.x] = e;
+}
+
+__global__ void __launch_bounds__(kWave) k_plain_reduce(const double* part, int n, double* E) {
+  const double e = wave_sum_array(part, n, threadIdx.x);
+  if (threadIdx.x == 0) *E = e;
+}
+
+__global__ void __launch_bounds__(256) k_copy(const float* src, float* dst, size_t n) {
+  for (size_t p = blockIdx.x * (size_t)256 + threadIdx.x; p < n; p += (size_t)gridDim.x * 256)
+    dst[p] = src ? src[p] : __builtin_nanf("");
+}
+
+inline int grid_for(size_t n) {
+  size_t b = (n + 255) / 256;
+  return (int)(b < 8192 ? (b ? b : 1) : 8192);
+}
+
+}  // namespace
+
+const void* persistent_kernel() { return (const void*)k_persistent; }
+
+hipError_t launch_persistent(const SolveArgs& a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_persistent, dim3(grid), dim3(kWG), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_reset_ctrl(int* ctrl, int n_ints, hipStream_t s) {
+  hipLaunchKernelGGL(k_reset, dim3(grid_for((size_t)n_ints)), dim3(256), 0, s, ctrl, n_ints,
+                     (const TaskDesc*)nullptr, 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_reset_tasks(int* ctrl, int n_ints, const TaskDesc* tasks, int n_tasks, hipStream_t s) {
+  const size_t n = (size_t)(n_ints > n_tasks ? n_ints : n_tasks);
+  hipLaunchKernelGGL(k_reset, dim3(grid_for(n)), dim3(256), 0, s, ctrl, n_ints, tasks, n_tasks);
+  return hipGetLastError();
+}
+
+hipError_t launch_plain_init(const TaskDesc* d_task, const SolveArgs& a, float* dst, hipStream_t s) {
+  const int L = a.levels;
+  const size_t n = (size_t)(a.H >> (L - 1)) * (a.W >> (L - 1));
+  hipLaunchKernelGGL(k_plain_init, dim3(grid_for(n)), dim3(kWG), 0, s, d_task, a, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_plain_prolong(const float* uc, float* uf, int h, int w, hipStream_t s) {
+  hipLaunchKernelGGL(k_plain_prolong, dim3(grid_for((size_t)h * w)), dim3(kWG), 0, s, uc, uf, h, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_plain_sweep(const float* R, const float* T, const float* u, float* un, int h, int w,
+                              double tau, double lam, int th, double* part, hipStream_t s) {
+  LevelView<float> V;
+  V.R = R;
+  V.T = T;
+  V.u = u;
+  V.out = un;
+  V.h = h;
+  V.w = w;
+  V.tau = tau;
+  V.lam = lam;
+  hipLaunchKernelGGL(k_plain_sweep, dim3(tiles_of(h, w, th)), dim3(kWG), 0, s, V, th, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_plain_reduce(const double* part, int n, double* E, hipStream_t s) {
+  hipLaunchKernelGGL(k_plain_reduce, dim3(1), dim3(kWave), 0, s, part, n, E);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(const float* src, float* dst, size_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy, dim3(grid_for(n)), dim3(256), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+
+}  // namespace rs

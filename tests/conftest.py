@@ -11,3 +11,13 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: long-running CPU test")
+
+
+def _ensure_library():
+    lib = os.path.join(ROOT, "paper_2010_12478_amd", "libregscan.so")
+    if not os.path.exists(lib):
+        from paper_2010_12478_amd.build import build
+        build()
+
+
+_ensure_library()

@@ -1,0 +1,101 @@
+"""Host-side checks of the C ABI: the library loads, exports every entry point
+the header declares, validates arguments, and its scan planner reproduces the
+oracle's plans bit for bit (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import plans as oplans
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "regscan.h")
+
+
+@pytest.fixture(scope="module")
+def rs():
+    import paper_2010_12478_amd as rs
+    return rs
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b((?:reg|scan)_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("reg_warp", "reg_energy_grad", "reg_solve_batch", "scan_run", "scan_plan",
+                     "reg_warp_adjoint", "reg_last_error", "reg_release"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(rs):
+    lib = ctypes.CDLL(rs.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    from paper_2010_12478_amd._lib import EXPORTS
+    assert sorted(EXPORTS) == declared_functions()
+
+
+def test_version(rs):
+    assert rs.lib.reg_version() == 100
+
+
+CASES = ([(algo, M, 0, "lf") for algo in ("seq", "dissemination", "lf", "bk")
+          for M in list(range(1, 34)) + [63, 64, 65, 127, 255, 256, 1000, 1023]]
+         + [("hier", M, S, g) for g in ("seq", "dissemination", "lf", "bk")
+            for M in (1, 2, 5, 16, 17, 100, 255, 1023) for S in (0, 1, 3, 8, 16, 32)])
+
+
+@pytest.mark.parametrize("algo,M,S,glob", CASES)
+def test_scan_plan_bit_exact_against_oracle(rs, algo, M, S, glob):
+    got, nl = rs.plan(M, algo, S, glob)
+    want, nl_want = oplans.make_plan(M, algo, S, glob)
+    assert nl == nl_want
+    assert got.shape == want.shape
+    assert np.array_equal(got, want)
+
+
+def test_scan_plan_large(rs):
+    for algo, S in (("hier", 64), ("lf", 0), ("dissemination", 0)):
+        got, _ = rs.plan(4095, algo, S, "lf")
+        want, _ = oplans.make_plan(4095, algo, S, "lf")
+        assert np.array_equal(got, want)
+
+
+def test_scan_plan_errors(rs):
+    lib = rs.lib
+    n, l = ctypes.c_int(), ctypes.c_int()
+    assert lib.scan_plan(0, 0, 0, 0, None, 0, ctypes.byref(n), ctypes.byref(l)) == -1
+    assert b"M = 0" in lib.reg_last_error()
+    assert lib.scan_plan(10, 7, 0, 0, None, 0, ctypes.byref(n), ctypes.byref(l)) == -1
+    assert lib.scan_plan(10, 4, 4, 9, None, 0, ctypes.byref(n), ctypes.byref(l)) == -1
+    # capacity too small: size still reported
+    buf = (ctypes.c_int32 * 7)()
+    assert lib.scan_plan(8, 1, 0, 0, ctypes.cast(buf, ctypes.c_void_p), 1, ctypes.byref(n),
+                         ctypes.byref(l)) == -1
+    assert n.value == 17
+
+
+def test_invalid_arguments_rejected_before_any_gpu_use(rs):
+    lib = rs.lib
+    from paper_2010_12478_amd._lib import params_struct
+    from synth.configs import SolverParams
+    p = params_struct(SolverParams(levels=3))
+    # 18x18 is not divisible by 4 -> rejected on the host
+    rc = lib.scan_run(ctypes.c_void_p(16), 4, 18, 18, ctypes.byref(p), 0, 0, 0, 1, 0,
+                      ctypes.c_void_p(16), None, None, None, None)
+    assert rc == -1 and b"divisible" in lib.reg_last_error()
+    bad = params_struct(SolverParams(levels=1, tau=-1.0))
+    rc = lib.scan_run(ctypes.c_void_p(16), 4, 16, 16, ctypes.byref(bad), 0, 0, 0, 1, 0,
+                      ctypes.c_void_p(16), None, None, None, None)
+    assert rc == -1 and b"tau" in lib.reg_last_error()
+    rc = lib.scan_run(ctypes.c_void_p(16), 1, 16, 16, ctypes.byref(p), 0, 0, 0, 1, 0,
+                      ctypes.c_void_p(16), None, None, None, None)
+    assert rc == -1
+    assert lib.reg_set_tuning(6, 0) == -1
+    assert lib.reg_set_tuning(0, 3) == -1

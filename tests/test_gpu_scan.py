@@ -1,0 +1,140 @@
+"""GPU parity of the series registration scan (scan_run) against the oracle run
+with the same plan, at small sizes spanning several tiles and at the full
+256 x 256 x 256-frame workload on sampled prefixes."""
+from dataclasses import replace
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import plans as oplans
+from oracle import registration as oreg
+from oracle.scan import run_scan
+from synth import get_config, make_series
+
+from _helpers import announce, host
+
+pytestmark = pytest.mark.gpu
+
+TOL_PX = 1e-3
+
+
+@pytest.fixture(scope="module")
+def rs():
+    import paper_2010_12478_amd as rs
+    rs.set_tuning(32, 16)
+    return rs
+
+
+def _check(rs_out, want, label):
+    phi0, u_pair, iters, status = (host(t) if t is not None else None for t in rs_out)
+    e_pair = np.abs(u_pair - want.u_pair).max()
+    e_phi = np.abs(phi0 - want.phi0).max()
+    d_it = np.abs(iters - want.iters).max()
+    print(f"{label}: max-abs phi0 {e_phi:.2e} px, u_pair {e_pair:.2e} px, "
+          f"max iteration difference {d_it}")
+    assert e_pair <= TOL_PX and e_phi <= TOL_PX
+    assert d_it == 0
+    return phi0
+
+
+def test_series16_sequential_fixed_iterations(rs):
+    """The CPU-sized workload: 16 frames 64x64, sequential recursion, 50 fixed updates."""
+    announce("series16 seq")
+    cfg = get_config(1)
+    S = make_series(cfg.series)
+    out = rs.scan_run(S.frames.cuda(), cfg.solver, "seq", mode="batched")
+    want = run_scan(S.frames.double().numpy(), cfg.solver, "seq")
+    _check(out, want, "series16 seq")
+    assert (host(out[2]) == 50).all() and (host(out[3]) == 0).all()
+
+
+@pytest.mark.parametrize("algo,chunk,glob", [("seq", 0, "lf"), ("dissemination", 0, "lf"),
+                                             ("lf", 0, "lf"), ("bk", 0, "lf"),
+                                             ("hier", 4, "lf"), ("hier", 3, "dissemination"),
+                                             ("hier", 5, "bk"), ("hier", 2, "seq")])
+def test_scan_algorithms_match_oracle(rs, algo, chunk, glob):
+    announce(f"scan {algo} chunk={chunk} global={glob}")
+    cfg = get_config(2, n_frames=14, height=64, width=96)
+    S = make_series(cfg.series)
+    p = replace(cfg.solver, max_iter=120)
+    out = rs.scan_run(S.frames.cuda(), p, algo, chunk, glob, mode="batched")
+    want = run_scan(S.frames.double().numpy(), p, algo, chunk, glob, workers=4)
+    phi0 = _check(out, want, f"{algo}/{chunk}/{glob}")
+    if algo != "seq":
+        seq = run_scan(S.frames.double().numpy(), p, "seq", workers=4)
+        print(f"deviation of {algo} from the sequential recursion: "
+              f"{np.abs(phi0 - seq.phi0).max():.3f} px (reported, not bounded)")
+
+
+def test_scan_ragged_three_levels(rs):
+    announce("scan ragged 3 levels")
+    cfg = get_config(3, n_frames=7, height=96, width=160, levels=3)
+    S = make_series(cfg.series)
+    p = replace(cfg.solver, max_iter=80)
+    out = rs.scan_run(S.frames.cuda(), p, "hier", 2, "lf")
+    want = run_scan(S.frames.double().numpy(), p, "hier", 2, "lf", workers=4)
+    _check(out, want, "ragged 3 levels")
+
+
+def test_plain_and_batched_scan_bitwise(rs):
+    announce("scan plain vs batched")
+    cfg = get_config(2, n_frames=9, height=64, width=64)
+    S = make_series(cfg.series)
+    p = replace(cfg.solver, max_iter=60)
+    a = rs.scan_run(S.frames.cuda(), p, "hier", 3, "lf", mode="plain")
+    b = rs.scan_run(S.frames.cuda(), p, "hier", 3, "lf", mode="batched")
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+
+
+def test_two_frames(rs):
+    announce("scan two frames")
+    cfg = get_config(1, n_frames=2)
+    S = make_series(cfg.series)
+    phi0, u_pair, iters, status = rs.scan_run(S.frames.cuda(), cfg.solver, "lf")
+    assert torch.equal(phi0, u_pair)
+    assert iters.shape == (1, 1)
+
+
+def _reg(args):
+    R, T, u0, p = args
+    return oreg.register(R, T, u0, p).u
+
+
+def test_full_size_series256_sampled_prefixes(rs):
+    """256 frames of 256x256, 2 levels, hierarchical plan (chunks of 16,
+    Ladner-Fischer global phase) in the benchmark's launch configuration.
+    The oracle recomputes, in the plan's combination order, the prefixes
+    phi_{0,1..6} of the first chunk, and the independent pairwise
+    registrations u_{k-1,k} for a sample of k across the series."""
+    announce("full size series256")
+    from concurrent.futures import ProcessPoolExecutor
+    import multiprocessing as mp
+    cfg = get_config(2)
+    S = make_series(cfg.series)
+    frames = S.frames
+    p = cfg.solver
+    phi0, u_pair, iters, status = (host(t) for t in rs.scan_run(frames.cuda(), p, cfg.algo, cfg.chunk,
+                                                                 cfg.global_algo, mode="batched"))
+    M = frames.shape[0] - 1
+    assert np.isfinite(phi0).all() and (status & 4 == 0).all()
+    ops, _ = oplans.make_plan(M, cfg.algo, cfg.chunk, cfg.global_algo)
+    fr = frames.double().numpy()
+    P = {f: oreg.pyramid(fr[f], p.levels) for f in list(range(7)) + [99, 100, 199, 200, 254, 255]}
+    ks = [1, 2, 3, 4, 5, 6, 100, 200, 255]
+    with ProcessPoolExecutor(max_workers=len(ks), mp_context=mp.get_context("fork")) as ex:
+        A = dict(zip(ks, ex.map(_reg, [(P[k - 1], P[k], None, p) for k in ks])))
+    for k in ks:
+        err = np.abs(u_pair[k - 1] - A[k]).max()
+        print(f"u_{k - 1},{k}: max-abs {err:.2e} px")
+        assert err <= TOL_PX, k
+    y = {1: A[1]}
+    for k in range(2, 7):
+        row = [r for r in ops if r[4] == 0 and r[6] == k][0]
+        assert row[5] == k - 1      # chunk 0 is a left fold
+        y[k] = oreg.register(P[0], P[k], oreg.compose(y[k - 1], A[k]), p).u
+    for k in range(1, 7):
+        err = np.abs(phi0[k - 1] - y[k]).max()
+        print(f"phi_0,{k}: max-abs {err:.2e} px")
+        assert err <= TOL_PX
