@@ -1,0 +1,202 @@
+"""Benchmark: series registration by prefix scan on one MI355X.
+
+Workload: 256 synthetic 256x256 lattice frames (drift <= 4 px, noise 0.1), a
+2-level pyramid, relative-decrease stopping (1e-5, at most 200 iterations per
+level), the hierarchical reduce-then-scan plan (chunks of 16 elements,
+Ladner-Fischer global phase).  One step = frame pyramid + the 255 pairwise
+registrations + every scan level, all through scan_run in batched mode
+(one persistent launch per scan level), inputs resident in HBM.
+
+Prints one JSON line with frames registered per second, the roofline of the
+dominant kernel (the persistent gradient-descent solver) from HIP events
+recorded by the library around each of its launches, the plain
+one-launch-per-iteration path on the same GPU, and the CPU oracle timed on a
+bounded sample on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "frames registered/sec over full prefix scan; warp/grad kernel HBM GB/s vs peak"
+PEAK_HBM_GBS = 8000.0
+SWEEP_BYTES = 24      # per pixel and kept update: R 4 + T 4 + u 8 read, u' 8 written
+EVAL_BYTES = 16       # per pixel of the final evaluation sweep (no update kept)
+FIELD_BYTES = 8       # one float32 displacement vector
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=0, help="registrations in the oracle sample")
+    return ap.parse_args()
+
+
+def algorithmic_bytes(iters, n_pair, H, W, levels, max_iter):
+    """Bytes the method must move in the solver launches: per level the kept
+    gradient-descent updates (24 B/px), the final evaluation sweep of a level
+    that stopped early (16 B/px), the prolongation (coarse read + fine write),
+    and the initial guess (identity: coarse write; composition: both fields
+    read at full resolution + coarse write)."""
+    import numpy as np
+    it = np.asarray(iters, dtype=np.int64)
+    total = 0
+    for l in range(levels):
+        px = (H >> l) * (W >> l)
+        k = it[:, l]
+        total += int(px * (SWEEP_BYTES * k + EVAL_BYTES * (k < max_iter)).sum())
+        if l < levels - 1:
+            total += int(it.shape[0] * FIELD_BYTES * ((H >> l) * (W >> l) + (H >> (l + 1)) * (W >> (l + 1))))
+    pxc = (H >> (levels - 1)) * (W >> (levels - 1))
+    n_ops = it.shape[0] - n_pair
+    total += int(n_pair * FIELD_BYTES * pxc)
+    total += int(n_ops * (2 * FIELD_BYTES * H * W + FIELD_BYTES * pxc))
+    return total
+
+
+def cpu_baseline(cfg, frames_cpu, n_total_regs, sample):
+    """Oracle throughput on the host cores: `sample` pairwise registrations of
+    the workload spread over one worker process per core, scaled to frames/s
+    assuming the full workload's registrations pack perfectly onto the same
+    cores (which favours the oracle: the scan's dependencies are ignored)."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+
+    from oracle.registration import pyramid, register
+
+    cores = min(len(os.sched_getaffinity(0)), 16)
+    sample = sample or 4 * cores
+    fr = frames_cpu.double().numpy()
+    p = cfg.solver
+    args = [(fr[k - 1], fr[k], p) for k in range(1, sample + 1)]
+    t0 = time.perf_counter()
+    with ProcessPoolExecutor(max_workers=cores, mp_context=mp.get_context("fork")) as ex:
+        res = list(ex.map(_oracle_pair, args))
+    wall = time.perf_counter() - t0
+    regs_per_s = sample / wall
+    M = fr.shape[0] - 1
+    t_full = n_total_regs / regs_per_s
+    return {"value": M / t_full, "unit": "frames/s", "cores": cores, "kind": "oracle",
+            "sample": (f"{sample} pairwise registrations (frames 0..{sample}) of the workload, "
+                       f"on {cores} worker processes (one per host core), {wall:.1f} s wall; scaled to the "
+                       f"workload's {n_total_regs} registrations assuming perfect packing"),
+            "mean_iterations": float(sum(sum(r) for r in res) / len(res))}
+
+
+def _oracle_pair(a):
+    from oracle.registration import pyramid, register
+    R, T, p = a
+    r = register(pyramid(R, p.levels), pyramid(T, p.levels), None, p)
+    return r.iters
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the scan shards across GPUs "
+              "by its reduce-then-scan hierarchy, which is not built here.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from synth import get_config, make_series
+
+    cfg = get_config(2)
+    spec, p = cfg.series, cfg.solver
+    t0 = time.perf_counter()
+    series = make_series(spec)          # host generation, seeded
+    gen_s = time.perf_counter() - t0
+    N, H, W = spec.n_frames, spec.height, spec.width
+    M = N - 1
+
+    lib_path = os.path.join(ROOT, "paper_2010_12478_amd", "libregscan.so")
+    if not os.path.exists(lib_path):
+        from paper_2010_12478_amd.build import build
+        build()
+    import paper_2010_12478_amd as rs
+
+    ops, n_levels = rs.plan(M, cfg.algo, cfg.chunk, cfg.global_algo)
+    n_regs = M + len(ops)
+
+    base = None
+    if not args.no_cpu_baseline:
+        base = cpu_baseline(cfg, series.frames, n_regs, args.cpu_sample)   # before any GPU use
+
+    dev = torch.device("cuda:0")
+    frames = series.frames.to(dev)
+    out = dict(phi0=torch.empty((M, 2, H, W), device=dev),
+               u_pair=torch.empty((M, 2, H, W), device=dev),
+               iters=torch.empty((n_regs, p.levels), dtype=torch.int32, device=dev),
+               status=torch.empty(n_regs, dtype=torch.int32, device=dev))
+
+    def step():
+        rs.scan_run(frames, p, cfg.algo, cfg.chunk, cfg.global_algo, mode="batched", out=out)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    kern_ms, kern_launches, alg_bytes = 0.0, 0, 0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+        ms, n = rs.last_solve_timing()        # waits for this step's solver events
+        kern_ms += ms
+        kern_launches += n
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = 1000.0 * wall / args.steps
+    iters = out["iters"].cpu().numpy()
+    status = out["status"].cpu().numpy()
+    alg_bytes = algorithmic_bytes(iters, M, H, W, p.levels, p.max_iter) * args.steps
+    achieved = alg_bytes / (kern_ms / 1000.0) / 1e9
+    value = M / (ms_per_step / 1000.0)
+
+    result = {
+        "metric": METRIC, "value": round(value, 3), "unit": "frames/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": cfg.name, "frames": N, "height": H, "width": W, "levels": p.levels,
+                   "plan": f"{cfg.algo}(chunk={cfg.chunk}, global={cfg.global_algo})",
+                   "plan_ops": int(len(ops)), "plan_levels": int(n_levels),
+                   "registrations": int(n_regs), "max_iter": p.max_iter, "rel_tol": p.rel_tol,
+                   "tau": p.tau, "lambda": p.lam, "storage": "f32", "parallelism": "single-gpu",
+                   "mean_iterations_per_level": [round(float(x), 2) for x in iters.mean(axis=0)],
+                   "maxiter_registrations": int((status & 1).sum()),
+                   "aborted_registrations": int((status & 4).sum())},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                     "kernel": "k_persistent (batched gradient-descent solver)",
+                     "kernel_ms_per_step": round(kern_ms / args.steps, 3),
+                     "launches_per_step": kern_launches // max(1, args.steps),
+                     "algorithmic_bytes_per_step": alg_bytes // args.steps},
+        "cpu_baseline": base,
+    }
+
+    if not args.no_plain:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rs.scan_run(frames, p, cfg.algo, cfg.chunk, cfg.global_algo, mode="plain", out=out)
+        torch.cuda.synchronize()
+        plain_s = time.perf_counter() - t0
+        result["plain"] = {"value": round(M / plain_s, 3), "unit": "frames/s", "steps": 1,
+                           "ms_per_step": round(1000 * plain_s, 1),
+                           "mode": "one registration at a time, one launch per iteration, host energy read-back"}
+        result["batched_over_plain"] = round(value / (M / plain_s), 2)
+    result["input_generation_s"] = round(gen_s, 2)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()
