@@ -197,7 +197,7 @@ Launch plan_launch(int n_tasks, int H, int W) {
 int run_batched(SolveArgs a, const TaskDesc* d_tasks, int n, hipStream_t s, bool timed) {
   if (n == 0) return REG_OK;
   const Launch L = plan_launch(n, a.H, a.W);
-  const int ctrl_ints = 64 + 32 * L.groups;
+  const int ctrl_ints = kCtrlHead + kCtrlGroup * L.groups;
   TRY(ensure(g.ctrl, (size_t)ctrl_ints * sizeof(int)));
   TRY(ensure(g.part, (size_t)L.groups * 2 * a.max_tiles * sizeof(double)));
   TRY(ensure(g.slots, (size_t)L.groups * a.slot_floats * sizeof(float)));

@@ -8,6 +8,8 @@
 namespace rs {
 
 constexpr int kMaxLevelsHost = 8;
+constexpr int kCtrlHead = 64;     // ints before the per-group control words
+constexpr int kCtrlGroup = 128;   // ints per group: [0] barrier, [4..5] ticket, [64..127] member XCC ids
 
 // One registration of a batch (device array element).
 struct TaskDesc {
@@ -32,7 +34,7 @@ struct SolveArgs {
   int g;                 // workgroups per registration (group)
   int th;                // tile rows
   int max_tiles;         // partial-sum slots per parity
-  int* ctrl;             // [0] work-queue ticket, [1] abort flag, groups at ctrl + 64 + 32*group
+  int* ctrl;             // [0] work-queue ticket, [1] abort flag, group q at ctrl + kCtrlHead + kCtrlGroup*q
   double* part;          // [groups][2][max_tiles]
   float* ws;             // [groups][slot_floats]
   size_t slot_floats;

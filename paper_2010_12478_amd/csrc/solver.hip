@@ -30,22 +30,40 @@ struct Group {
   int g, member, id;
   int* bar;      // arrival counter (monotonic)
   int* task;     // [2] ticket broadcast
+  int* xcc;      // [g] XCC id of every member
   int epoch;
+  bool local;    // every member runs on the same XCD (verified at launch)
 };
+
+__device__ __forceinline__ int xcc_id() {
+  return __builtin_amdgcn_s_getreg((20) | (0 << 6) | (3 << 11));   // HW_REG_XCC_ID[3:0]
+}
 
 // Barrier over the g workgroups of a group.  Returns false if the run has been
 // aborted (by this or another workgroup's watchdog); all workgroups then leave.
+//
+// When all members share one XCD (G.local) they also share its L2, and since
+// the vector L1 is write-through, a member's stores are visible to the others
+// once they have completed (vmcnt 0) and the readers have dropped their own
+// L1 lines: the L2 write-back of an agent-scope release is not needed.  The
+// readers still use the agent-scope acquire (buffer_inv sc1): measured on
+// gfx950, the workgroup-scope invalidate (buffer_inv sc0) leaves another CU's
+// stale L1 lines in place.  Otherwise the agent-scope release and acquire make
+// the data coherent across XCDs.
 __device__ bool group_sync(Group& G, int* abort_flag, unsigned spin_limit, int* s_flag) {
   if (G.g == 1) {
     __syncthreads();
     return true;
   }
-  __threadfence();   // each thread's global writes visible at agent scope
+  if (G.local)
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  else
+    __threadfence();
   __syncthreads();
   G.epoch += 1;
   if (threadIdx.x == 0) {
     int ok = 1;
-    __hip_atomic_fetch_add(G.bar, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_add(G.bar, 1, G.local ? __ATOMIC_RELAXED : __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     const int target = G.epoch * G.g;
     unsigned spins = 0;
     while (ld_relaxed(G.bar) < target) {
@@ -58,7 +76,7 @@ __device__ bool group_sync(Group& G, int* abort_flag, unsigned spin_limit, int* 
         ok = 0;
         break;
       }
-      __builtin_amdgcn_s_sleep(2);
+      __builtin_amdgcn_s_sleep(1);
     }
     *s_flag = ok;
   }
@@ -181,17 +199,35 @@ __global__ void __launch_bounds__(kWG) k_persistent(SolveArgs a) {
   G.g = a.g;
   G.member = lb % a.g;
   G.id = (lb / a.g) * 8 + xcd;
-  G.bar = a.ctrl + 64 + 32 * G.id;
+  G.bar = a.ctrl + kCtrlHead + kCtrlGroup * G.id;
   G.task = G.bar + 4;
+  G.xcc = G.bar + 64;
   G.epoch = 0;
+  G.local = false;
   int* queue = a.ctrl;
   int* abort_flag = a.ctrl + 1;
   double* part = a.part + (size_t)G.id * 2 * a.max_tiles;
   float* slot = a.ws + (size_t)G.id * a.slot_floats;
   int par = 0, tpar = 0;
 
-  if (G.member == 0 && threadIdx.x == 0) G.task[0] = atomicAdd(queue, 1);
-  if (!group_sync(G, abort_flag, a.spin_limit, &s_flag)) return;
+  // Control words are written and read with agent-scope atomics only, so they
+  // are coherent whatever the barrier flavour (the data buffers are not).
+  if (threadIdx.x == 0) __hip_atomic_store(&G.xcc[G.member], xcc_id(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (G.member == 0 && threadIdx.x == 0)
+    __hip_atomic_store(&G.task[0], atomicAdd(queue, 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (!group_sync(G, abort_flag, a.spin_limit, &s_flag)) return;   // agent scope: always coherent
+  if (G.g > 1) {
+    if (threadIdx.x == 0) {
+      int same = 1;
+      const int mine = __hip_atomic_load(&G.xcc[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      for (int m = 1; m < G.g; ++m)
+        same &= __hip_atomic_load(&G.xcc[m], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == mine;
+      s_task = same;
+    }
+    __syncthreads();
+    G.local = s_task != 0;
+    __syncthreads();
+  }
   for (;;) {
     if (threadIdx.x == 0) s_task = ld_relaxed(&G.task[tpar]);
     __syncthreads();
@@ -199,7 +235,8 @@ __global__ void __launch_bounds__(kWG) k_persistent(SolveArgs a) {
     if (t >= a.n_tasks) break;
     if (!run_task(a, a.tasks[t], G, slot, part, par, red, &s_E, &s_flag)) return;
     tpar ^= 1;
-    if (G.member == 0 && threadIdx.x == 0) G.task[tpar] = atomicAdd(queue, 1);
+    if (G.member == 0 && threadIdx.x == 0)
+      __hip_atomic_store(&G.task[tpar], atomicAdd(queue, 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (!group_sync(G, abort_flag, a.spin_limit, &s_flag)) return;
   }
 }
