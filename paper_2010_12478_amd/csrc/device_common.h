@@ -62,6 +62,53 @@ __device__ __forceinline__ double bilin_value(const S* __restrict__ img, int H, 
          wy * (ox * (double)img[yb * W + xa] + wx * (double)img[yb * W + xb]);
 }
 
+// Loads of data that other workgroups of the same launch write (displacement
+// fields, per-tile energies) go through a buffer descriptor with the
+// device-scope policy (sc1): they miss the CU's L1 but allocate in and hit the
+// XCD's L2, so no stale L1 line is returned once the writer's stores have
+// reached that L2 (measured on gfx950: loads with the default or workgroup
+// policy return stale lines; sc1 or nontemporal loads do not, and
+// nontemporal ones also stop the line from staying in L2).  The base pointer
+// must be uniform across the wavefront: it is moved to scalar registers from
+// lane 0.
+constexpr int kAuxSC1 = 16;
+
+// A pointer every lane of the wavefront holds, moved to scalar registers.
+__device__ __forceinline__ void* uniform_ptr(const void* p) {
+  const uint64_t v = (uint64_t)p;
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return (void*)(((uint64_t)hi << 32) | lo);
+}
+
+struct SharedBuf {
+  __amdgpu_buffer_rsrc_t r;
+  __device__ __forceinline__ explicit SharedBuf(const void* base)
+      : r(__builtin_amdgcn_make_buffer_rsrc(uniform_ptr(base), 0, -1, 0x00020000)) {}
+  __device__ __forceinline__ float f32(int i) const {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, i * 4, 0, kAuxSC1));
+  }
+  __device__ __forceinline__ double f64(int i) const {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, i * 8, 0, kAuxSC1));
+  }
+  template <typename S>
+  __device__ __forceinline__ S load(int i) const;
+};
+template <>
+__device__ __forceinline__ float SharedBuf::load<float>(int i) const { return f32(i); }
+template <>
+__device__ __forceinline__ double SharedBuf::load<double>(int i) const { return f64(i); }
+
+// Bilinear value of a shared field (see SharedBuf) with clamped taps.
+__device__ __forceinline__ double bilin_value_shared(const SharedBuf& img, int H, int W, int x0, int y0,
+                                                     double wx, double wy) {
+  const int xa = clampi(x0, 0, W - 1), xb = clampi(x0 + 1, 0, W - 1);
+  const int ya = clampi(y0, 0, H - 1), yb = clampi(y0 + 1, 0, H - 1);
+  const double ox = 1.0 - wx, oy = 1.0 - wy;
+  return oy * (ox * (double)img.f32(ya * W + xa) + wx * (double)img.f32(ya * W + xb)) +
+         wy * (ox * (double)img.f32(yb * W + xa) + wx * (double)img.f32(yb * W + xb));
+}
+
 // Butterfly sum over the 64 lanes of a wavefront: every lane ends with the
 // same, order-fixed total.
 __device__ __forceinline__ double wave_sum(double v) {
@@ -74,8 +121,9 @@ __device__ __forceinline__ double wave_sum(double v) {
 // p[l], p[l+64], ... in sequence, then the butterfly.  Used for every
 // per-tile energy total so that all execution paths agree bitwise.
 __device__ __forceinline__ double wave_sum_array(const double* p, int n, int lane) {
+  const SharedBuf buf(p);
   double acc = 0.0;
-  for (int i = lane; i < n; i += kWave) acc += p[i];
+  for (int i = lane; i < n; i += kWave) acc += buf.f64(i);
   return wave_sum(acc);
 }
 

@@ -58,8 +58,8 @@ struct State {
   int device = -1;
   int n_cu = 0;
   int blocks_per_cu = 0;
-  int tile_rows = 32;
-  int max_group = 16;
+  int tile_rows = 16;
+  int max_group = 32;
   unsigned spin_limit = 1u << 22;   // ~seconds of polling before the watchdog aborts a run
   DevBuf pyr, slots, part, ctrl, tasks, nodes, upair, iters, status, misc, lvl;
   double* h_E = nullptr;   // pinned host scalar for the plain path
@@ -112,8 +112,8 @@ int ensure(DevBuf& b, size_t bytes) {
 int check_dims(int B, int H, int W) {
   if (B < 0) return fail(REG_E_INVALID, "batch size %d < 0", B);
   if (H < 1 || W < 1) return fail(REG_E_INVALID, "image size %dx%d must be positive", H, W);
-  if (H > 16384 || W > 16384 || (long long)H * W > (1LL << 28))
-    return fail(REG_E_INVALID, "image size %dx%d exceeds 16384 per side or 2^28 pixels", H, W);
+  if (H > 16384 || W > 16384 || (long long)H * W > (1LL << 26))
+    return fail(REG_E_INVALID, "image size %dx%d exceeds 16384 per side or 2^26 pixels", H, W);
   return REG_OK;
 }
 

@@ -9,7 +9,8 @@ namespace rs {
 
 constexpr int kMaxLevelsHost = 8;
 constexpr int kCtrlHead = 64;     // ints before the per-group control words
-constexpr int kCtrlGroup = 128;   // ints per group: [0] barrier, [4..5] ticket, [64..127] member XCC ids
+constexpr int kCtrlGroup = 256;   // ints per group: [0..63] member arrival epochs, [64..65] ticket,
+                                  // [128..191] member XCC ids
 
 // One registration of a batch (device array element).
 struct TaskDesc {

@@ -40,7 +40,7 @@ __global__ void __launch_bounds__(kEW) k_prolong(const float* __restrict__ uc, f
     const int r = (int)(t - b * Hf * Wf);
     const int y = r / Wf, x = r - y * Wf;
     double vx, vy;
-    prolong_pixel(uc + b * 2 * hc * wc, hc, wc, x, y, vx, vy);
+    prolong_pixel<false>(uc + b * 2 * hc * wc, hc, wc, x, y, vx, vy);   // base varies per lane
     float* o = uf + b * 2 * Hf * Wf;
     o[r] = (float)vx;
     o[(size_t)Hf * Wf + r] = (float)vy;

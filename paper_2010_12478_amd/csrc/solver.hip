@@ -28,7 +28,7 @@ __device__ __forceinline__ int ld_relaxed(const int* p) {
 
 struct Group {
   int g, member, id;
-  int* bar;      // arrival counter (monotonic)
+  int* arrive;   // [g] epoch each member has reached (one word per member)
   int* task;     // [2] ticket broadcast
   int* xcc;      // [g] XCC id of every member
   int epoch;
@@ -44,12 +44,13 @@ __device__ __forceinline__ int xcc_id() {
 //
 // When all members share one XCD (G.local) they also share its L2, and since
 // the vector L1 is write-through, a member's stores are visible to the others
-// once they have completed (vmcnt 0) and the readers have dropped their own
-// L1 lines: the L2 write-back of an agent-scope release is not needed.  The
-// readers still use the agent-scope acquire (buffer_inv sc1): measured on
-// gfx950, the workgroup-scope invalidate (buffer_inv sc0) leaves another CU's
-// stale L1 lines in place.  Otherwise the agent-scope release and acquire make
-// the data coherent across XCDs.
+// once they have completed (vmcnt 0), provided every read of such data misses
+// the reader's L1 (SharedBuf): neither the L2 write-back of an agent-scope
+// release nor the L1/L2 invalidation of an agent-scope acquire is needed, so
+// the XCD's L2 keeps the frames and fields between iterations.  (Measured on
+// gfx950: the workgroup-scope invalidate, buffer_inv sc0, leaves another CU's
+// stale L1 lines in place; sc1 loads do not return them.)  Otherwise
+// the agent-scope release and acquire make the data coherent across XCDs.
 __device__ bool group_sync(Group& G, int* abort_flag, unsigned spin_limit, int* s_flag) {
   if (G.g == 1) {
     __syncthreads();
@@ -61,27 +62,31 @@ __device__ bool group_sync(Group& G, int* abort_flag, unsigned spin_limit, int* 
     __threadfence();
   __syncthreads();
   G.epoch += 1;
-  if (threadIdx.x == 0) {
+  if (threadIdx.x < kWave) {   // wavefront 0 announces arrival and polls every member's word
+    const int lane = threadIdx.x;
+    if (lane == 0)
+      __hip_atomic_store(&G.arrive[G.member], G.epoch, G.local ? __ATOMIC_RELAXED : __ATOMIC_RELEASE,
+                         __HIP_MEMORY_SCOPE_AGENT);
     int ok = 1;
-    __hip_atomic_fetch_add(G.bar, 1, G.local ? __ATOMIC_RELAXED : __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    const int target = G.epoch * G.g;
     unsigned spins = 0;
-    while (ld_relaxed(G.bar) < target) {
+    for (;;) {
+      const int v = lane < G.g ? ld_relaxed(&G.arrive[lane]) : G.epoch;
+      if (__all(v >= G.epoch)) break;
       if (ld_relaxed(abort_flag)) {
         ok = 0;
         break;
       }
       if (++spins > spin_limit) {
-        __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (lane == 0) __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         ok = 0;
         break;
       }
       __builtin_amdgcn_s_sleep(1);
     }
-    *s_flag = ok;
+    if (lane == 0) *s_flag = ok;
   }
   __syncthreads();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  if (!G.local) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   return *s_flag != 0;
 }
 
@@ -126,7 +131,7 @@ __device__ bool run_task(const SolveArgs& a, const TaskDesc& d, Group& G, float*
       for (int p = first; p < n; p += stride) {
         const int y = p / w, x = p - y * w;
         double vx, vy;
-        prolong_pixel<float>(cur, h >> 1, w >> 1, x, y, vx, vy);
+        prolong_pixel<true>(cur, h >> 1, w >> 1, x, y, vx, vy);
         dst[p] = (float)vx;
         dst[(size_t)n + p] = (float)vy;
       }
@@ -179,7 +184,8 @@ __device__ bool run_task(const SolveArgs& a, const TaskDesc& d, Group& G, float*
   if (dead) {
     for (size_t p = first; p < nf; p += stride) d.out[p] = __builtin_nanf("");
   } else if (cur != d.out) {
-    for (size_t p = first; p < nf; p += stride) d.out[p] = cur[p];
+    const SharedBuf src(cur);
+    for (size_t p = first; p < nf; p += stride) d.out[p] = src.f32((int)p);
   }
   if (G.member == 0 && threadIdx.x == 0) {
     if (d.iters)
@@ -189,7 +195,7 @@ __device__ bool run_task(const SolveArgs& a, const TaskDesc& d, Group& G, float*
   return true;
 }
 
-__global__ void __launch_bounds__(kWG) k_persistent(SolveArgs a) {
+__global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) k_persistent(SolveArgs a) {
   __shared__ double red[kWG / kWave];
   __shared__ double s_E;
   __shared__ int s_flag;
@@ -199,9 +205,10 @@ __global__ void __launch_bounds__(kWG) k_persistent(SolveArgs a) {
   G.g = a.g;
   G.member = lb % a.g;
   G.id = (lb / a.g) * 8 + xcd;
-  G.bar = a.ctrl + kCtrlHead + kCtrlGroup * G.id;
-  G.task = G.bar + 4;
-  G.xcc = G.bar + 64;
+  int* gctl = a.ctrl + kCtrlHead + kCtrlGroup * G.id;
+  G.arrive = gctl;
+  G.task = gctl + 64;
+  G.xcc = gctl + 128;
   G.epoch = 0;
   G.local = false;
   int* queue = a.ctrl;
@@ -269,7 +276,7 @@ __global__ void __launch_bounds__(kWG) k_plain_prolong(const float* uc, float* u
   for (int p = blockIdx.x * kWG + threadIdx.x; p < n; p += gridDim.x * kWG) {
     const int y = p / w, x = p - y * w;
     double vx, vy;
-    prolong_pixel<float>(uc, h >> 1, w >> 1, x, y, vx, vy);
+    prolong_pixel<true>(uc, h >> 1, w >> 1, x, y, vx, vy);
     uf[p] = (float)vx;
     uf[(size_t)n + p] = (float)vy;
   }

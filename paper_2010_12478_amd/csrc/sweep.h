@@ -15,7 +15,8 @@
 // Layout: a tile is 64 columns (one wavefront, lane = column) by `th` rows;
 // the 4 wavefronts of the workgroup take th/4 consecutive rows each and walk
 // down their column keeping the rows above / below in registers, so every u
-// value is loaded once per sweep.  Horizontal neighbours come from the
+// value is loaded once per sweep (through SharedBuf: other workgroups of a
+// persistent launch write these fields).  Horizontal neighbours come from the
 // adjacent lanes (cross-lane shuffles); lanes 0 and 63 read the one column
 // outside the tile.  R and u are read and u' written fully coalesced; the 4
 // taps of T are gathered through the vector L1/L2 (the displacement field is
@@ -58,8 +59,8 @@ __device__ double sweep_tile(const LevelView<S>& L, int tile, int th, double* re
   const int y0 = ty * th + wave * rpw;
   const int y1 = min(y0 + rpw, h);
   const size_t hw = (size_t)h * w;
-  const S* __restrict__ ux = L.u;
-  const S* __restrict__ uy = L.u + hw;
+  const SharedBuf ub(L.u);           // plane 0 at 0, plane 1 at hw
+  const int ihw = (int)hw;
   const S* __restrict__ Rr = L.R;
   const double lam = L.lam, tau = L.tau;
   double acc = 0.0, gacc = 0.0;
@@ -67,17 +68,17 @@ __device__ double sweep_tile(const LevelView<S>& L, int tile, int th, double* re
   if (y0 < y1) {
     S ax[kRB + 2], ay[kRB + 2];   // column values of rows yb-1 .. yb+kRB
     const int ym = y0 > 0 ? y0 - 1 : 0;
-    ax[0] = ux[ym * w + xc];
-    ay[0] = uy[ym * w + xc];
-    ax[1] = ux[y0 * w + xc];
-    ay[1] = uy[y0 * w + xc];
+    ax[0] = ub.load<S>(ym * w + xc);
+    ay[0] = ub.load<S>(ihw + ym * w + xc);
+    ax[1] = ub.load<S>(y0 * w + xc);
+    ay[1] = ub.load<S>(ihw + y0 * w + xc);
     for (int yb = y0; yb < y1; yb += kRB) {
       S rr[kRB];
 #pragma unroll
       for (int r = 0; r < kRB; ++r) {
         const int yn = min(yb + 1 + r, h - 1);
-        ax[r + 2] = ux[yn * w + xc];
-        ay[r + 2] = uy[yn * w + xc];
+        ax[r + 2] = ub.load<S>(yn * w + xc);
+        ay[r + 2] = ub.load<S>(ihw + yn * w + xc);
         rr[r] = Rr[min(yb + r, h - 1) * w + xc];
       }
 #pragma unroll
@@ -88,12 +89,12 @@ __device__ double sweep_tile(const LevelView<S>& L, int tile, int th, double* re
         S lxs = __shfl_up(cxs, 1, kWave), lys = __shfl_up(cys, 1, kWave);
         S rxs = __shfl_down(cxs, 1, kWave), rys = __shfl_down(cys, 1, kWave);
         if (lane == 0 && x > 0) {
-          lxs = ux[y * w + x - 1];
-          lys = uy[y * w + x - 1];
+          lxs = ub.load<S>(y * w + x - 1);
+          lys = ub.load<S>(ihw + y * w + x - 1);
         }
         if (lane == kWave - 1 && x + 1 < w) {
-          rxs = ux[y * w + x + 1];
-          rys = uy[y * w + x + 1];
+          rxs = ub.load<S>(y * w + x + 1);
+          rys = ub.load<S>(ihw + y * w + x + 1);
         }
         const bool hl = x > 0, hr = x + 1 < w, hu = y > 0, hd = y + 1 < h;
         int ix, iy;
@@ -180,15 +181,23 @@ __device__ __forceinline__ void init_pixel(int kind, const S* __restrict__ ua, c
 }
 
 // Prolongation of a coarse displacement [2][hc][wc] to fine pixel (x, y):
-// 2 * uc((x - 1/2)/2, (y - 1/2)/2), bilinear with clamped taps.
-template <typename S>
-__device__ __forceinline__ void prolong_pixel(const S* __restrict__ uc, int hc, int wc, int x, int y,
+// 2 * uc((x - 1/2)/2, (y - 1/2)/2), bilinear with clamped taps.  SHARED: uc
+// is written by other workgroups of the launch and is wave-uniform (loads
+// through SharedBuf); otherwise plain loads.
+template <bool SHARED>
+__device__ __forceinline__ void prolong_pixel(const float* __restrict__ uc, int hc, int wc, int x, int y,
                                               double& vx, double& vy) {
   const int x0 = (x - 1) >> 1, y0 = (y - 1) >> 1;      // floor((x - 1/2) / 2)
   const double wx = (x & 1) ? 0.25 : 0.75;
   const double wy = (y & 1) ? 0.25 : 0.75;
-  vx = 2.0 * bilin_value(uc, hc, wc, x0, y0, wx, wy);
-  vy = 2.0 * bilin_value(uc + (size_t)hc * wc, hc, wc, x0, y0, wx, wy);
+  if (SHARED) {
+    const SharedBuf bx(uc), by(uc + (size_t)hc * wc);
+    vx = 2.0 * bilin_value_shared(bx, hc, wc, x0, y0, wx, wy);
+    vy = 2.0 * bilin_value_shared(by, hc, wc, x0, y0, wx, wy);
+  } else {
+    vx = 2.0 * bilin_value(uc, hc, wc, x0, y0, wx, wy);
+    vy = 2.0 * bilin_value(uc + (size_t)hc * wc, hc, wc, x0, y0, wx, wy);
+  }
 }
 
 }  // namespace rs
