@@ -10,7 +10,7 @@ constexpr int kWG = 256;        // threads of every tile workgroup (4 wavefronts
 constexpr int kWave = 64;
 constexpr int kTileW = 64;      // a tile row is one wavefront wide
 constexpr int kMaxLevels = 8;
-constexpr int kRB = 4;          // rows per register batch in the sweep
+constexpr int kRB = 2;          // rows per register batch in the sweep
 
 __host__ __device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
@@ -81,23 +81,27 @@ __device__ __forceinline__ void* uniform_ptr(const void* p) {
   return (void*)(((uint64_t)hi << 32) | lo);
 }
 
-struct SharedBuf {
+// Buffer descriptor over a wave-uniform base: 32-bit element offsets keep the
+// per-lane address arithmetic in one register.  AUX is the cache policy
+// (0: default, kAuxSC1: miss the L1, see above).
+template <int AUX>
+struct BufView {
   __amdgpu_buffer_rsrc_t r;
-  __device__ __forceinline__ explicit SharedBuf(const void* base)
+  __device__ __forceinline__ explicit BufView(const void* base)
       : r(__builtin_amdgcn_make_buffer_rsrc(uniform_ptr(base), 0, -1, 0x00020000)) {}
   __device__ __forceinline__ float f32(int i) const {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, i * 4, 0, kAuxSC1));
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, i * 4, 0, AUX));
   }
   __device__ __forceinline__ double f64(int i) const {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, i * 8, 0, kAuxSC1));
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, i * 8, 0, AUX));
   }
   template <typename S>
-  __device__ __forceinline__ S load(int i) const;
+  __device__ __forceinline__ S load(int i) const {
+    if constexpr (sizeof(S) == 4) return f32(i); else return f64(i);
+  }
 };
-template <>
-__device__ __forceinline__ float SharedBuf::load<float>(int i) const { return f32(i); }
-template <>
-__device__ __forceinline__ double SharedBuf::load<double>(int i) const { return f64(i); }
+using SharedBuf = BufView<kAuxSC1>;   // data written by other workgroups of the launch
+using ReadBuf = BufView<0>;           // data no one writes during the launch
 
 // Bilinear value of a shared field (see SharedBuf) with clamped taps.
 __device__ __forceinline__ double bilin_value_shared(const SharedBuf& img, int H, int W, int x0, int y0,

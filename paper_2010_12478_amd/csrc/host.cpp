@@ -1,6 +1,6 @@
 // C interface of the registration library: argument validation, workspace,
 // batch / scan orchestration and the plain and batched execution paths.
-#include "../../include/regscan.h"
+#include "regscan.h"
 
 #include <hip/hip_runtime.h>
 

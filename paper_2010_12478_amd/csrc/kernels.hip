@@ -128,12 +128,8 @@ __global__ void __launch_bounds__(kWG) k_energy_tiles(const S* __restrict__ R, c
   L.w = W;
   L.tau = 0.0;
   L.lam = lam;
-  double gn = 0.0;
-  const double E = sweep_tile<S, WRITE, GNORM>(L, blockIdx.x, th, red, &gn);
-  if (threadIdx.x == 0) {
-    part[(size_t)b * nt + blockIdx.x] = E;
-    if (GNORM) gpart[(size_t)b * nt + blockIdx.x] = gn;
-  }
+  sweep_tiles<S, WRITE, GNORM>(L, blockIdx.x, gridDim.x, th, red, part + (size_t)b * nt,
+                               gpart + (size_t)b * nt);
 }
 
 __global__ void __launch_bounds__(kWave) k_sum_tiles(const double* part, const double* gpart, int nt,

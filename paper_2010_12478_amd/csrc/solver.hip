@@ -153,10 +153,7 @@ __device__ bool run_task(const SolveArgs& a, const TaskDesc& d, Group& G, float*
       V.u = cur;
       V.out = other;
       double* pp = part + (size_t)par * a.max_tiles;
-      for (int tile = G.member; tile < nt; tile += G.g) {
-        const double e = sweep_tile<float, SW_UPDATE, false>(V, tile, a.th, red, nullptr);
-        if (threadIdx.x == 0) pp[tile] = e;
-      }
+      sweep_tiles<float, SW_UPDATE, false>(V, G.member, G.g, a.th, red, pp, nullptr);
       if (!group_sync(G, abort_flag, a.spin_limit, s_flag)) return false;
       if (threadIdx.x < kWave) {
         const double E = wave_sum_array(pp, nt, threadIdx.x);
@@ -284,8 +281,7 @@ __global__ void __launch_bounds__(kWG) k_plain_prolong(const float* uc, float* u
 
 __global__ void __launch_bounds__(kWG) k_plain_sweep(LevelView<float> V, int th, double* part) {
   __shared__ double red[kWG / kWave];
-  const double e = sweep_tile<float, SW_UPDATE, false>(V, blockIdx.x, th, red, nullptr);
-  if (threadIdx.x == 0) part[blockIdx.x] = e;
+  sweep_tiles<float, SW_UPDATE, false>(V, blockIdx.x, gridDim.x, th, red, part, nullptr);
 }
 
 __global__ void __launch_bounds__(kWave) k_plain_reduce(const double* part, int n, double* E) {

@@ -42,104 +42,180 @@ struct LevelView {
 __host__ __device__ inline int tiles_x(int w) { return (w + kTileW - 1) / kTileW; }
 __host__ __device__ inline int tiles_of(int h, int w, int th) { return tiles_x(w) * ((h + th - 1) / th); }
 
-// Returns the tile energy in thread 0 (other threads: unspecified).  With
-// GNORM, *gn (thread 0) receives sum_x |g(x)|^2 of the tile.  `red` is
-// __shared__ double[kWG / kWave].  Must be called by all kWG threads.
+// Registers of one unit of work of a wavefront: rows [yb, ye) (at most kRB)
+// of one tile, lane = column.
+template <typename S>
+struct Unit {
+  int tile, yb, ye;
+  S ax[kRB + 2], ay[kRB + 2];   // u at rows yb-1 .. yb+kRB of this lane's column (rows clamped)
+  S rr[kRB];                     // R at rows yb .. yb+kRB-1
+  S hx[kRB], hy[kRB];            // lane 0: u at column x-1, lane 63: u at column x+1
+};
+
+// Sweeps the tiles first, first + stride, ... of level L (all of them for
+// stride 1 and first 0 is not implied: pass the workgroup's own share).  For
+// every tile the energy (and with GNORM the squared gradient norm) is summed
+// in a fixed order: per lane over its rows in order, the butterfly over the
+// wavefront, then the 4 wavefronts in order; thread 0 stores it to
+// part[tile] (gpart[tile]).  Must be called by all kWG threads.
+//
+// Each wavefront walks a sequence of units (a tile's rows, th/4 per
+// wavefront, in batches of kRB rows; then the next tile).  The loop is
+// software-pipelined: the gathers of T for unit i are issued before the u, R
+// and halo loads of unit i + 1, and unit i is computed while those are in
+// flight, so each unit exposes one memory round trip instead of two.
 // Arithmetic is double; the stored type S is float (or double).
 template <typename S, int WRITE, bool GNORM>
-__device__ double sweep_tile(const LevelView<S>& L, int tile, int th, double* red, double* gn) {
+__device__ void sweep_tiles(const LevelView<S>& L, int first, int stride, int th, double* red, double* part,
+                            double* gpart) {
   const int h = L.h, w = L.w;
   const int ntx = tiles_x(w);
-  const int tx = tile % ntx, ty = tile / ntx;
+  const int nt = tiles_of(h, w, th);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int rpw = th >> 2;
-  const int x = tx * kTileW + lane;
-  const bool vx = x < w;
-  const int xc = vx ? x : w - 1;
-  const int y0 = ty * th + wave * rpw;
-  const int y1 = min(y0 + rpw, h);
+  const int upt = (rpw + kRB - 1) / kRB;            // units per tile and wavefront
+  const int my_tiles = first < nt ? (nt - first + stride - 1) / stride : 0;
+  const int n_units = my_tiles * upt;
   const size_t hw = (size_t)h * w;
-  const SharedBuf ub(L.u);           // plane 0 at 0, plane 1 at hw
   const int ihw = (int)hw;
-  const S* __restrict__ Rr = L.R;
+  const SharedBuf ub(L.u);                          // plane 0 at 0, plane 1 at hw
+  const ReadBuf rb(L.R), tb(L.T);
   const double lam = L.lam, tau = L.tau;
-  double acc = 0.0, gacc = 0.0;
 
-  if (y0 < y1) {
-    S ax[kRB + 2], ay[kRB + 2];   // column values of rows yb-1 .. yb+kRB
-    const int ym = y0 > 0 ? y0 - 1 : 0;
-    ax[0] = ub.load<S>(ym * w + xc);
-    ay[0] = ub.load<S>(ihw + ym * w + xc);
-    ax[1] = ub.load<S>(y0 * w + xc);
-    ay[1] = ub.load<S>(ihw + y0 * w + xc);
-    for (int yb = y0; yb < y1; yb += kRB) {
-      S rr[kRB];
+  auto setup = [&](int i, Unit<S>& U) {
+    const int k = i / upt, b = i - k * upt;
+    U.tile = first + k * stride;
+    const int ty = U.tile / ntx;
+    const int ys = ty * th + wave * rpw;
+    const int yend = min(ys + rpw, h);
+    U.yb = ys + b * kRB;
+    U.ye = min(U.yb + kRB, yend);
+  };
+  auto load = [&](Unit<S>& U) {
+    if (U.yb >= U.ye) return;
+    const int x = (U.tile % ntx) * kTileW + lane;
+    const int xc = x < w ? x : w - 1;
+#pragma unroll
+    for (int r = 0; r < kRB + 2; ++r) {
+      // rows clamped to the image: at the top / bottom edge the missing
+      // neighbour row is the pixel's own row
+      const int row = __mul24(clampi(U.yb - 1 + r, 0, h - 1), w);
+      U.ax[r] = ub.load<S>(row + xc);
+      U.ay[r] = ub.load<S>(ihw + row + xc);
+    }
+#pragma unroll
+    for (int r = 0; r < kRB; ++r) U.rr[r] = rb.load<S>(__mul24(min(U.yb + r, h - 1), w) + xc);
+    if (lane == 0 || lane == kWave - 1) {
+      // the column outside the tile, clamped to the image: at the image edge
+      // it is the pixel's own column, so the missing difference is exactly 0
+      const int xn = clampi(lane == 0 ? x - 1 : x + 1, 0, w - 1);
 #pragma unroll
       for (int r = 0; r < kRB; ++r) {
-        const int yn = min(yb + 1 + r, h - 1);
-        ax[r + 2] = ub.load<S>(yn * w + xc);
-        ay[r + 2] = ub.load<S>(ihw + yn * w + xc);
-        rr[r] = Rr[min(yb + r, h - 1) * w + xc];
+        const int row = __mul24(min(U.yb + r, h - 1), w);
+        U.hx[r] = ub.load<S>(row + xn);
+        U.hy[r] = ub.load<S>(ihw + row + xn);
       }
+    }
+  };
+
+  Unit<S> A, B;
+  double accE = 0.0, accG = 0.0;
+  if (n_units > 0) {
+    setup(0, A);
+    load(A);
+  }
+  for (int i = 0; i < n_units; ++i) {
+    const int x = (A.tile % ntx) * kTileW + lane;
+    const bool vx = x < w;
+    const int xc = vx ? x : w - 1;
+    // gathers of T for this unit
+    S taps[kRB][4];
+    S fxs[kRB], fys[kRB];      // exact: the fraction of a stored value fits its type
+    if (A.yb < A.ye) {
 #pragma unroll
       for (int r = 0; r < kRB; ++r) {
-        const int y = yb + r;
-        if (y >= y1) break;
-        const S cxs = ax[r + 1], cys = ay[r + 1];
-        S lxs = __shfl_up(cxs, 1, kWave), lys = __shfl_up(cys, 1, kWave);
-        S rxs = __shfl_down(cxs, 1, kWave), rys = __shfl_down(cys, 1, kWave);
-        if (lane == 0 && x > 0) {
-          lxs = ub.load<S>(y * w + x - 1);
-          lys = ub.load<S>(ihw + y * w + x - 1);
-        }
-        if (lane == kWave - 1 && x + 1 < w) {
-          rxs = ub.load<S>(y * w + x + 1);
-          rys = ub.load<S>(ihw + y * w + x + 1);
-        }
-        const bool hl = x > 0, hr = x + 1 < w, hu = y > 0, hd = y + 1 < h;
         int ix, iy;
         double fx, fy;
-        cell_of(cxs, ix, fx);
-        cell_of(cys, iy, fy);
-        double s, dsx, dsy;
-        bilin(L.T, h, w, xc + ix, y + iy, fx, fy, s, dsx, dsy);
+        cell_of(A.ax[r + 1], ix, fx);
+        cell_of(A.ay[r + 1], iy, fy);
+        fxs[r] = (S)fx;
+        fys[r] = (S)fy;
+        const int x0 = xc + ix, y0 = min(A.yb + r, h - 1) + iy;
+        const int xa = clampi(x0, 0, w - 1), xb = clampi(x0 + 1, 0, w - 1);
+        const int ya = __mul24(clampi(y0, 0, h - 1), w), yb = __mul24(clampi(y0 + 1, 0, h - 1), w);
+        taps[r][0] = tb.load<S>(ya + xa);
+        taps[r][1] = tb.load<S>(ya + xb);
+        taps[r][2] = tb.load<S>(yb + xa);
+        taps[r][3] = tb.load<S>(yb + xb);
+      }
+    }
+    // loads of the next unit, in flight during this unit's arithmetic
+    if (i + 1 < n_units) {
+      setup(i + 1, B);
+      load(B);
+    }
+    if (A.yb < A.ye) {
+#pragma unroll
+      for (int r = 0; r < kRB; ++r) {
+        const int y = A.yb + r;
+        if (y >= A.ye) break;
+        const S cxs = A.ax[r + 1], cys = A.ay[r + 1];
+        // neighbours: lanes past the right edge hold column w - 1, so every
+        // missing neighbour equals the pixel's own value (difference +0.0,
+        // the same as leaving the term out)
+        S lxs = __shfl_up(cxs, 1, kWave), lys = __shfl_up(cys, 1, kWave);
+        S rxs = __shfl_down(cxs, 1, kWave), rys = __shfl_down(cys, 1, kWave);
+        if (lane == 0) {
+          lxs = A.hx[r];
+          lys = A.hy[r];
+        }
+        if (lane == kWave - 1) {
+          rxs = A.hx[r];
+          rys = A.hy[r];
+        }
+        const double fx = fxs[r], fy = fys[r];
+        const double i00 = taps[r][0], i01 = taps[r][1], i10 = taps[r][2], i11 = taps[r][3];
+        const double ox = 1.0 - fx, oy = 1.0 - fy;
+        const double s = oy * (ox * i00 + fx * i01) + fy * (ox * i10 + fx * i11);
+        const double dsx = oy * (i01 - i00) + fy * (i11 - i10);
+        const double dsy = ox * (i10 - i00) + fx * (i11 - i01);
         const double cx = cxs, cy = cys;
         const double lx = lxs, ly = lys, rx = rxs, ry = rys;
-        const double upx = ax[r], upy = ay[r], dnx = ax[r + 2], dny = ay[r + 2];
-        const double res = s - (double)rr[r];
-        const double drx = hr ? rx - cx : 0.0, dry = hr ? ry - cy : 0.0;
-        const double ddx = hd ? dnx - cx : 0.0, ddy = hd ? dny - cy : 0.0;
+        const double upx = A.ax[r], upy = A.ay[r], dnx = A.ax[r + 2], dny = A.ay[r + 2];
+        const double res = s - (double)A.rr[r];
+        const double drx = rx - cx, dry = ry - cy;
+        const double ddx = dnx - cx, ddy = dny - cy;
         const double e = res * res + lam * ((drx * drx + ddx * ddx) + (dry * dry + ddy * ddy));
-        const double nbx = ((hl ? cx - lx : 0.0) + (hr ? cx - rx : 0.0)) +
-                           ((hu ? cx - upx : 0.0) + (hd ? cx - dnx : 0.0));
-        const double nby = ((hl ? cy - ly : 0.0) + (hr ? cy - ry : 0.0)) +
-                           ((hu ? cy - upy : 0.0) + (hd ? cy - dny : 0.0));
+        const double nbx = ((cx - lx) + (cx - rx)) + ((cx - upx) + (cx - dnx));
+        const double nby = ((cy - ly) + (cy - ry)) + ((cy - upy) + (cy - dny));
         const double gx = 2.0 * res * dsx + 2.0 * lam * nbx;
         const double gy = 2.0 * res * dsy + 2.0 * lam * nby;
         if (vx) {
-          acc += e;
+          accE += e;
+          const int o = __mul24(y, w) + x;
           if (WRITE == SW_UPDATE) {
-            L.out[y * w + x] = (S)(cx - tau * gx);
-            L.out[hw + y * w + x] = (S)(cy - tau * gy);
+            L.out[o] = (S)(cx - tau * gx);
+            L.out[hw + o] = (S)(cy - tau * gy);
           } else if (WRITE == SW_GRAD) {
-            L.out[y * w + x] = (S)gx;
-            L.out[hw + y * w + x] = (S)gy;
+            L.out[o] = (S)gx;
+            L.out[hw + o] = (S)gy;
           }
-          if (GNORM) gacc += gx * gx + gy * gy;
+          if (GNORM) accG += gx * gx + gy * gy;
         }
       }
-      ax[0] = ax[kRB];
-      ay[0] = ay[kRB];
-      ax[1] = ax[kRB + 1];
-      ay[1] = ay[kRB + 1];
     }
+    if ((i + 1) % upt == 0) {   // last unit of this tile: order-fixed block sums
+      const double E = block_sum(accE, red);
+      if (threadIdx.x == 0) part[A.tile] = E;
+      accE = 0.0;
+      if (GNORM) {
+        const double G = block_sum(accG, red);
+        if (threadIdx.x == 0) gpart[A.tile] = G;
+        accG = 0.0;
+      }
+    }
+    A = B;
   }
-  const double E = block_sum(acc, red);
-  if (GNORM) {
-    const double G = block_sum(gacc, red);
-    if (threadIdx.x == 0) *gn = G;
-  }
-  return E;
 }
 
 // Initial guess of a registration on its coarsest level (pixel (X, Y)):
