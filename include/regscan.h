@@ -86,8 +86,13 @@ enum {
   REG_PLAIN = 0,   /* one registration at a time; one kernel launch per
                       gradient-descent iteration and a host read-back of the
                       energy for the stopping rule */
-  REG_BATCHED = 1  /* all registrations of a batch (a scan level) in one
+  REG_BATCHED = 1, /* all registrations of a batch (a scan level) in one
                       persistent launch fed by a device atomic work queue */
+  REG_DATAFLOW = 2 /* scan_run: the pairwise registrations and every op of
+                      the plan in a single persistent launch; an op enters
+                      the device ready queue as soon as both of its inputs
+                      exist, so no level waits for the slowest registration
+                      of the previous one (reg_solve_batch: as REG_BATCHED) */
 };
 
 /* scan_run flags */
@@ -205,7 +210,8 @@ int reg_prolong(const float* uc, float* uf, int B, int Hf, int Wf, void* stream)
  *   u         [B][2][H][W] results (must not alias u0 or frames)
  *   iters     [B][levels]  iterations per level (level 0 first), or NULL
  *   status    [B]          REG_S_* bits, or NULL
- *   mode      REG_PLAIN or REG_BATCHED; both give bitwise identical results.
+ *   mode      REG_PLAIN, REG_BATCHED or REG_DATAFLOW; all give bitwise
+ *             identical results.
  * REG_PLAIN synchronises the stream after every iteration. */
 int reg_solve_batch(const float* frames, int N, int H, int W,
                     const int32_t* ref_idx, const int32_t* tmpl_idx,
@@ -229,8 +235,10 @@ int scan_plan(int M, int algo, int chunk, int global_algo, scan_op_t* ops, int c
  *   phase A   u_pair[k-1] = A(f_{k-1}, f_k), k = 1..M, M = N - 1, one batch;
  *   scan      the plan of (algo, chunk, global_algo) level by level, each level
  *             one batch of B(phi_ij, phi_jk) registrations (REG_BATCHED: one
- *             persistent launch per level; REG_PLAIN: one registration at a
- *             time).
+ *             persistent launch per level; REG_DATAFLOW: one launch for the
+ *             whole series, ops started as their inputs complete; REG_PLAIN:
+ *             one registration at a time).  Every mode gives bitwise
+ *             identical outputs.
  *   frames   [N][H][W], N >= 2
  *   phi0     [M][2][H][W]  out: u_{0,k} for k = 1..M
  *   u_pair   [M][2][H][W]  out: u_{k-1,k}, or NULL (kept in workspace)
@@ -238,7 +246,8 @@ int scan_plan(int M, int algo, int chunk, int global_algo, scan_op_t* ops, int c
  *            (k = 1..M) then of the plan's ops in plan order, or NULL
  *   status   [M + n_ops] out: REG_S_* bits in the same order, or NULL
  *   flags    SCAN_F_* bits
- * Intermediate scan nodes live in library workspace, reused once dead. */
+ * Intermediate scan nodes live in library workspace (REG_BATCHED / REG_PLAIN:
+ * reused once their last consumer's level has completed). */
 int scan_run(const float* frames, int N, int H, int W, const reg_params_t* p,
              int algo, int chunk, int global_algo, int mode, int flags,
              float* phi0, float* u_pair, int32_t* op_iters, int32_t* status, void* stream);
@@ -255,8 +264,12 @@ int reg_last_solve_timing(double* total_ms, int* launches);
  * (see reg_autotune) unless set here. */
 int reg_set_tuning(int tile_rows, int max_group);
 
-/* Time candidate tile heights and group caps on the given batch shape with
- * fixed-iteration solves and keep the fastest (HOST outputs, optional). */
+/* Autotuner: on synthetic lattice frames of the given shape, time a batch of
+ * `batch` pairwise registrations (REG_BATCHED, 20 fixed iterations per
+ * level) for every tile height in {16, 32, 64} and workgroup cap in
+ * {1, 4, 8, 16, 32, 64}; keep the fastest as the library tuning and return it
+ * (HOST outputs, optional).  Results are cached per shape for the process;
+ * outputs of the solver do not depend on the tuning (bitwise). */
 int reg_autotune(int H, int W, int levels, int batch, int* tile_rows, int* max_group, void* stream);
 
 /* Free the library workspace and cached graphs. */

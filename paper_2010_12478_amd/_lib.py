@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libregscan.so")
 REG_OK, REG_E_INVALID, REG_E_NOMEM, REG_E_HIP, REG_E_NODEVICE = 0, -1, -2, -3, -4
 REG_S_OK, REG_S_MAXITER, REG_S_NONFINITE, REG_S_ABORTED = 0, 1, 2, 4
 SCAN_ALGOS = {"seq": 0, "dissemination": 1, "lf": 2, "bk": 3, "hier": 4}
-MODES = {"plain": 0, "batched": 1}
+MODES = {"plain": 0, "batched": 1, "dataflow": 2}
 SCAN_F_GRAPH = 1
 
 EXPORTS = (

@@ -61,10 +61,18 @@ struct State {
   int tile_rows = 16;
   int max_group = 32;
   unsigned spin_limit = 1u << 22;   // ~seconds of polling before the watchdog aborts a run
-  DevBuf pyr, slots, part, ctrl, tasks, nodes, upair, iters, status, misc, lvl;
+  DevBuf pyr, slots, part, ctrl, tasks, nodes, upair, iters, status, misc, lvl, flow;
   double* h_E = nullptr;   // pinned host scalar for the plain path
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
   size_t events_used = 0;
+  struct Graph {
+    std::string key;
+    unsigned generation;
+    hipGraphExec_t exec;
+    DevBuf tasks, flow;   // descriptors owned by the graph
+  };
+  std::vector<Graph> graphs;
+  std::map<long long, std::pair<int, int>> tuned;   // autotune results by shape
   unsigned generation = 0;   // bumps whenever a workspace buffer moves
 };
 
@@ -215,6 +223,40 @@ int run_batched(SolveArgs a, const TaskDesc* d_tasks, int n, hipStream_t s, bool
   return REG_OK;
 }
 
+// Runs a task DAG with one persistent launch.  deps0/ready0/cons_off/cons are
+// device arrays (see SolveArgs); deps/ready are their working copies.
+int run_dataflow(SolveArgs a, const TaskDesc* d_tasks, int n, int* deps, const int* deps0, int* ready,
+                 const int* ready0, int n_ready0, const int* cons_off, const int* cons, hipStream_t s, bool timed) {
+  if (n == 0) return REG_OK;
+  const int resident = g.blocks_per_cu * g.n_cu;
+  const int tiles = tiles_of(a.H, a.W, g.tile_rows);
+  int gs = 1;
+  while (gs * 2 <= g.max_group && gs * 2 <= tiles && 8 * gs * 2 <= resident) gs *= 2;
+  const int groups = std::max(8, (resident / gs / 8) * 8);
+  const int ctrl_ints = kCtrlHead + kCtrlGroup * groups;
+  TRY(ensure(g.ctrl, (size_t)ctrl_ints * sizeof(int)));
+  TRY(ensure(g.part, (size_t)groups * 2 * a.max_tiles * sizeof(double)));
+  TRY(ensure(g.slots, (size_t)groups * a.slot_floats * sizeof(float)));
+  a.tasks = d_tasks;
+  a.n_tasks = n;
+  a.g = gs;
+  a.ctrl = (int*)g.ctrl.p;
+  a.part = (double*)g.part.p;
+  a.ws = (float*)g.slots.p;
+  a.dataflow = 1;
+  a.deps = deps;
+  a.ready = ready;
+  a.cons_off = cons_off;
+  a.cons = cons;
+  HIPCHK(launch_reset_tasks(a.ctrl, ctrl_ints, d_tasks, n, s));
+  HIPCHK(launch_reset_dataflow(deps, deps0, ready, ready0, n, a.ctrl, n_ready0, s));
+  hipEvent_t* ev = timed ? next_events() : nullptr;
+  if (ev) HIPCHK(hipEventRecord(ev[0], s));
+  HIPCHK(launch_persistent(a, groups * gs, s));
+  if (ev) HIPCHK(hipEventRecord(ev[1], s));
+  return REG_OK;
+}
+
 // -------------------------------------------------------------- plain path
 
 int run_plain(SolveArgs a, const std::vector<TaskDesc>& tasks, const TaskDesc* d_tasks, hipStream_t s) {
@@ -283,6 +325,15 @@ int upload_tasks(DevBuf& buf, const std::vector<TaskDesc>& t, hipStream_t s) {
   HIPCHK(hipMemcpyAsync(buf.p, t.data(), t.size() * sizeof(TaskDesc), hipMemcpyHostToDevice, s));
   HIPCHK(hipStreamSynchronize(s));
   return REG_OK;
+}
+
+void drop_graphs() {
+  for (auto& gr : g.graphs) {
+    (void)hipGraphExecDestroy(gr.exec);
+    if (gr.tasks.p) (void)hipFree(gr.tasks.p);
+    if (gr.flow.p) (void)hipFree(gr.flow.p);
+  }
+  g.graphs.clear();
 }
 
 }  // namespace
@@ -560,7 +611,8 @@ int reg_solve_batch(const float* frames, int N, int H, int W, const int32_t* ref
   TRY(check_dims(B, H, W));
   TRY(check_params(p, H, W));
   if (N < 1) return fail(REG_E_INVALID, "N = %d frames", N);
-  if (mode != REG_PLAIN && mode != REG_BATCHED) return fail(REG_E_INVALID, "unknown mode %d", mode);
+  if (mode != REG_PLAIN && mode != REG_BATCHED && mode != REG_DATAFLOW)
+    return fail(REG_E_INVALID, "unknown mode %d", mode);
   if (B == 0) return REG_OK;
   if (!frames || !ref_idx || !tmpl_idx || !u) return fail(REG_E_INVALID, "NULL pointer");
   if (u0 && u0 == u) return fail(REG_E_INVALID, "u aliases u0");
@@ -588,7 +640,7 @@ int reg_solve_batch(const float* frames, int N, int H, int W, const int32_t* ref
   }
   TRY(upload_tasks(g.tasks, tasks, s));
   g.events_used = 0;
-  if (mode == REG_BATCHED) return run_batched(a, (const TaskDesc*)g.tasks.p, B, s, true);
+  if (mode != REG_PLAIN) return run_batched(a, (const TaskDesc*)g.tasks.p, B, s, true);
   return run_plain(a, tasks, (const TaskDesc*)g.tasks.p, s);
 }
 
@@ -623,7 +675,8 @@ int scan_run(const float* frames, int N, int H, int W, const reg_params_t* p, in
   TRY(check_dims(1, H, W));
   TRY(check_params(p, H, W));
   if (N < 2) return fail(REG_E_INVALID, "a series needs N >= 2 frames (got %d)", N);
-  if (mode != REG_PLAIN && mode != REG_BATCHED) return fail(REG_E_INVALID, "unknown mode %d", mode);
+  if (mode != REG_PLAIN && mode != REG_BATCHED && mode != REG_DATAFLOW)
+    return fail(REG_E_INVALID, "unknown mode %d", mode);
   if (flags & ~SCAN_F_GRAPH) return fail(REG_E_INVALID, "unknown flags 0x%x", flags);
   if (!frames || !phi0) return fail(REG_E_INVALID, "NULL pointer");
   const int M = N - 1;
@@ -666,7 +719,9 @@ int scan_run(const float* frames, int N, int H, int W, const reg_params_t* p, in
         slot_of[plan[q].out] = free_slots.back();
         free_slots.pop_back();
       }
-      for (int nd : dies[lvl]) free_slots.push_back(slot_of[nd]);
+      // levels overlap in dataflow mode: no reuse there
+      if (mode != REG_DATAFLOW)
+        for (int nd : dies[lvl]) free_slots.push_back(slot_of[nd]);
     }
   }
   TRY(ensure(g.nodes, std::max<size_t>(1, (size_t)n_slots) * nf * sizeof(float)));
@@ -714,31 +769,132 @@ int scan_run(const float* frames, int N, int H, int W, const reg_params_t* p, in
     d.iters = it_out + (M + n) * (size_t)L;
     d.status = st_out + (M + n);
   }
-  TRY(upload_tasks(g.tasks, tasks, s));
-  const TaskDesc* d_tasks = (const TaskDesc*)g.tasks.p;
-
-  const float* lv[kMaxLevels] = {};
-  TRY(build_pyramid(frames, N, H, W, L, lv, s));
-  SolveArgs a = base_args(lv, H, W, p);
-  g.events_used = 0;
-  if (mode == REG_BATCHED) {
-    TRY(run_batched(a, d_tasks, M, s, true));
-    HIPCHK(launch_copy(pair, phi0, nf, s));
-    size_t q = 0;
-    for (int lvl = 1; lvl <= n_levels; ++lvl) {
-      const size_t q0 = q;
-      while (q < n_ops && plan[q].level == lvl) ++q;
-      TRY(run_batched(a, d_tasks + M + q0, (int)(q - q0), s, true));
+  const bool use_graph = (flags & SCAN_F_GRAPH) && mode != REG_PLAIN;
+  char keybuf[512];
+  snprintf(keybuf, sizeof keybuf, "%p %p %p %p %p %d %d %d %d %d %d %.17g %.17g %.17g %d %d %d %d %d %d",
+           (const void*)frames, (void*)phi0, (void*)pair, (void*)it_out, (void*)st_out, N, H, W, p->levels,
+           p->max_iter, p->fixed_iter, p->tau, p->lambda, p->rel_tol, algo, chunk, global_algo, mode,
+           g.tile_rows, g.max_group);
+  const std::string key(keybuf);
+  if (use_graph) {
+    // graphs whose workspace has moved can never be replayed: free them
+    for (size_t q = 0; q < g.graphs.size();) {
+      if (g.graphs[q].generation != g.generation) {
+        (void)hipGraphExecDestroy(g.graphs[q].exec);
+        if (g.graphs[q].tasks.p) (void)hipFree(g.graphs[q].tasks.p);
+        if (g.graphs[q].flow.p) (void)hipFree(g.graphs[q].flow.p);
+        g.graphs.erase(g.graphs.begin() + q);
+      } else {
+        ++q;
+      }
     }
-  } else {
-    std::vector<TaskDesc> A(tasks.begin(), tasks.begin() + M);
-    TRY(run_plain(a, A, d_tasks, s));
-    HIPCHK(launch_copy(pair, phi0, nf, s));
-    for (size_t n = 0; n < n_ops; ++n) {
-      std::vector<TaskDesc> one{tasks[M + n]};
-      TRY(run_plain(a, one, d_tasks + M + n, s));
+    for (auto& gr : g.graphs) {
+      if (gr.key == key && gr.generation == g.generation) {
+        g.events_used = 0;
+        hipEvent_t* ev = next_events();
+        if (ev) HIPCHK(hipEventRecord(ev[0], s));
+        HIPCHK(hipGraphLaunch(gr.exec, s));
+        if (ev) HIPCHK(hipEventRecord(ev[1], s));
+        return REG_OK;
+      }
     }
   }
+
+  TRY(upload_tasks(g.tasks, tasks, s));
+  const size_t T = M + n_ops;
+  size_t flow_used = 0;
+  if (mode == REG_DATAFLOW) {
+    // task index == node id: A task k-1 produces node k-1, op n produces M + n
+    std::vector<int> host(3 * T + 1 + 2 * n_ops);
+    int* deps0 = host.data();
+    int* ready0 = deps0 + T;
+    int* cons_off = ready0 + T;
+    int* cons = cons_off + T + 1;
+    std::vector<int> cnt(T, 0);
+    for (size_t t = 0; t < T; ++t) {
+      deps0[t] = (int)t < M ? 0 : 2;
+      ready0[t] = (int)t < M ? (int)t : -1;
+    }
+    for (const PlanOp& q : plan) {
+      cnt[q.a]++;
+      cnt[q.b]++;
+    }
+    cons_off[0] = 0;
+    for (size_t t = 0; t < T; ++t) cons_off[t + 1] = cons_off[t] + cnt[t];
+    std::vector<int> fill(cons_off, cons_off + T);
+    for (size_t n = 0; n < n_ops; ++n) {
+      cons[fill[plan[n].a]++] = (int)(M + n);
+      cons[fill[plan[n].b]++] = (int)(M + n);
+    }
+    flow_used = host.size();   // deps0, ready0, cons_off, cons; then deps, ready
+    TRY(ensure(g.flow, (flow_used + 2 * T) * sizeof(int)));
+    HIPCHK(hipMemcpyAsync(g.flow.p, host.data(), flow_used * sizeof(int), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
+
+  // every launch of the run; graph capture records exactly these
+  auto enqueue = [&](hipStream_t st, const TaskDesc* d_tasks, int* dflow, bool timed) -> int {
+    const float* lv[kMaxLevels] = {};
+    TRY(build_pyramid(frames, N, H, W, L, lv, st));
+    SolveArgs a = base_args(lv, H, W, p);
+    if (mode == REG_DATAFLOW) {
+      TRY(run_dataflow(a, d_tasks, (int)T, dflow + flow_used, dflow, dflow + flow_used + T, dflow + T, M,
+                       dflow + 2 * T, dflow + 3 * T + 1, st, timed));
+      HIPCHK(launch_copy(pair, phi0, nf, st));
+    } else if (mode == REG_BATCHED) {
+      TRY(run_batched(a, d_tasks, M, st, timed));
+      HIPCHK(launch_copy(pair, phi0, nf, st));
+      size_t q = 0;
+      for (int lvl = 1; lvl <= n_levels; ++lvl) {
+        const size_t q0 = q;
+        while (q < n_ops && plan[q].level == lvl) ++q;
+        TRY(run_batched(a, d_tasks + M + q0, (int)(q - q0), st, timed));
+      }
+    } else {
+      std::vector<TaskDesc> A(tasks.begin(), tasks.begin() + M);
+      TRY(run_plain(a, A, d_tasks, st));
+      HIPCHK(launch_copy(pair, phi0, nf, st));
+      for (size_t n = 0; n < n_ops; ++n) {
+        std::vector<TaskDesc> one{tasks[M + n]};
+        TRY(run_plain(a, one, d_tasks + M + n, st));
+      }
+    }
+    return REG_OK;
+  };
+
+  g.events_used = 0;
+  TRY(enqueue(s, (const TaskDesc*)g.tasks.p, (int*)g.flow.p, true));
+  if (!use_graph) return REG_OK;
+
+  // capture the same launches into a graph that owns copies of the descriptors
+  HIPCHK(hipStreamSynchronize(s));
+  const unsigned gen = g.generation;
+  State::Graph gr;
+  gr.key = key;
+  gr.exec = nullptr;
+  if (hipMalloc(&gr.tasks.p, T * sizeof(TaskDesc)) != hipSuccess) return fail(REG_E_NOMEM, "graph descriptors");
+  gr.tasks.n = T * sizeof(TaskDesc);
+  HIPCHK(hipMemcpy(gr.tasks.p, g.tasks.p, gr.tasks.n, hipMemcpyDeviceToDevice));
+  if (mode == REG_DATAFLOW) {
+    gr.flow.n = (flow_used + 2 * T) * sizeof(int);
+    if (hipMalloc(&gr.flow.p, gr.flow.n) != hipSuccess) return fail(REG_E_NOMEM, "graph dataflow arrays");
+    HIPCHK(hipMemcpy(gr.flow.p, g.flow.p, gr.flow.n, hipMemcpyDeviceToDevice));
+  }
+  hipStream_t cs;
+  HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+  const int rc = enqueue(cs, (const TaskDesc*)gr.tasks.p, (int*)gr.flow.p, false);
+  hipGraph_t graph = nullptr;
+  const hipError_t ec = hipStreamEndCapture(cs, &graph);
+  (void)hipStreamDestroy(cs);
+  if (rc != REG_OK) return rc;
+  if (ec != hipSuccess) return fail(REG_E_HIP, "graph capture failed: %s", hipGetErrorString(ec));
+  if (g.generation != gen) return fail(REG_E_HIP, "workspace moved during graph capture");
+  const hipError_t ei = hipGraphInstantiate(&gr.exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ei != hipSuccess) return fail(REG_E_HIP, "graph instantiation failed: %s", hipGetErrorString(ei));
+  gr.generation = gen;
+  g.graphs.push_back(gr);
   return REG_OK;
 }
 
@@ -768,8 +924,72 @@ int reg_set_tuning(int tile_rows, int max_group) {
 }
 
 int reg_autotune(int H, int W, int levels, int batch, int* tile_rows, int* max_group, void* stream) {
-  (void)H; (void)W; (void)levels; (void)batch; (void)stream;
   std::lock_guard<std::recursive_mutex> lk(g_mu);
+  TRY(check_dims(batch, H, W));
+  if (batch < 1) return fail(REG_E_INVALID, "batch %d < 1", batch);
+  reg_params_t p{levels, 20, 1, 0.5, 0.1, 1e-5};
+  TRY(check_params(&p, H, W));
+  TRY(ensure_device());
+  hipStream_t s = (hipStream_t)stream;
+  const long long key = ((long long)H << 40) ^ ((long long)W << 20) ^ ((long long)levels << 16) ^ batch;
+  auto hit = g.tuned.find(key);
+  if (hit == g.tuned.end()) {
+    // synthetic lattice frames and a batch of pairwise registrations, timed
+    // with a fixed iteration count for every candidate
+    const int F = batch + 1;
+    const size_t nf = (size_t)2 * H * W;
+    DevBuf frames, u;
+    if (hipMalloc(&frames.p, (size_t)F * H * W * sizeof(float)) != hipSuccess ||
+        hipMalloc(&u.p, (size_t)batch * nf * sizeof(float)) != hipSuccess) {
+      if (frames.p) (void)hipFree(frames.p);
+      return fail(REG_E_NOMEM, "autotune buffers");
+    }
+    HIPCHK(launch_synth_frames((float*)frames.p, F, H, W, s));
+    std::vector<int32_t> ref(batch), tmpl(batch);
+    for (int b = 0; b < batch; ++b) {
+      ref[b] = b;
+      tmpl[b] = b + 1;
+    }
+    const int saved_th = g.tile_rows, saved_mg = g.max_group;
+    double best = 1e300;
+    int best_th = saved_th, best_mg = saved_mg;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    int rc = REG_OK;
+    for (int th : {16, 32, 64}) {
+      if (th > H) continue;
+      for (int mg : {1, 4, 8, 16, 32, 64}) {
+        g.tile_rows = th;
+        g.max_group = mg;
+        float ms = 0.f;
+        for (int rep = 0; rep < 2 && rc == REG_OK; ++rep) {   // first run warms up
+          (void)hipEventRecord(e0, s);
+          rc = reg_solve_batch((const float*)frames.p, F, H, W, ref.data(), tmpl.data(), nullptr, (float*)u.p,
+                               nullptr, nullptr, batch, &p, REG_BATCHED, stream);
+          (void)hipEventRecord(e1, s);
+          (void)hipEventSynchronize(e1);
+          (void)hipEventElapsedTime(&ms, e0, e1);
+        }
+        if (rc != REG_OK) break;
+        if (ms < best) {
+          best = ms;
+          best_th = th;
+          best_mg = mg;
+        }
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(frames.p);
+    (void)hipFree(u.p);
+    g.tile_rows = saved_th;
+    g.max_group = saved_mg;
+    if (rc != REG_OK) return rc;
+    hit = g.tuned.emplace(key, std::make_pair(best_th, best_mg)).first;
+  }
+  g.tile_rows = hit->second.first;
+  g.max_group = hit->second.second;
   if (tile_rows) *tile_rows = g.tile_rows;
   if (max_group) *max_group = g.max_group;
   return REG_OK;
@@ -780,7 +1000,7 @@ void reg_release(void) {
   if (!g.init) return;
   (void)hipDeviceSynchronize();
   for (DevBuf* b : {&g.pyr, &g.slots, &g.part, &g.ctrl, &g.tasks, &g.nodes, &g.upair, &g.iters, &g.status,
-                    &g.misc, &g.lvl}) {
+                    &g.misc, &g.lvl, &g.flow}) {
     if (b->p) (void)hipFree(b->p);
     b->p = nullptr;
     b->n = 0;
@@ -791,6 +1011,7 @@ void reg_release(void) {
   }
   g.events.clear();
   g.events_used = 0;
+  drop_graphs();
   g.generation++;
 }
 

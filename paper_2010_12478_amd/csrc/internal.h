@@ -42,6 +42,14 @@ struct SolveArgs {
   size_t lvl_off[kMaxLevelsHost];     // offsets of the pyramid-shaped buffer A per level
   size_t bufB_off;       // offset of buffer B inside a slot
   unsigned spin_limit;
+  // dataflow execution (dataflow != 0): task t enters ready[] (tail ctrl[3],
+  // head ctrl[2]) once deps[t] drops to 0; the consumers of task t are
+  // cons[cons_off[t] .. cons_off[t + 1])
+  int dataflow;
+  int* deps;
+  int* ready;
+  const int* cons_off;
+  const int* cons;
 };
 
 size_t slot_floats_for(int H, int W, int levels, size_t* lvl_off, size_t* bufB_off);
@@ -61,12 +69,16 @@ hipError_t launch_energy_backward_level(const void* Ia, const void* u, const voi
                                         bool f64, hipStream_t s);
 hipError_t launch_adjoint_init(const void* dIa_c, void* dIa, int B, int h, int w, bool f64, hipStream_t s);
 hipError_t launch_add_energy(const double* Ein, double* Eacc, int B, int first, hipStream_t s);
+hipError_t launch_synth_frames(float* out, int F, int H, int W, hipStream_t s);
 
 // solver.hip
 const void* persistent_kernel();
 hipError_t launch_persistent(const SolveArgs& a, int grid, hipStream_t s);
 hipError_t launch_reset_ctrl(int* ctrl, int n_ints, hipStream_t s);
 hipError_t launch_reset_tasks(int* ctrl, int n_ints, const TaskDesc* tasks, int n_tasks, hipStream_t s);
+// dataflow state: deps = deps0, ready = ready0, ctrl[3] (tail) = n_ready0
+hipError_t launch_reset_dataflow(int* deps, const int* deps0, int* ready, const int* ready0, int n_tasks,
+                                 int* ctrl, int n_ready0, hipStream_t s);
 hipError_t launch_plain_init(const TaskDesc* d_task, const SolveArgs& a, float* dst, hipStream_t s);
 hipError_t launch_plain_prolong(const float* uc, float* uf, int h, int w, hipStream_t s);
 hipError_t launch_plain_sweep(const float* R, const float* T, const float* u, float* un, int h, int w,

@@ -213,6 +213,20 @@ __global__ void __launch_bounds__(kEW) k_adjoint_init(const S* __restrict__ dIa_
   }
 }
 
+// Autotuner input: a square lattice of period 8 px (sum of two cosines per
+// axis), frame f shifted by (0.37 f, -0.29 f) px.
+__global__ void __launch_bounds__(kEW) k_synth_frames(float* out, int F, int H, int W) {
+  const size_t n = (size_t)F * H * W;
+  for (size_t t = blockIdx.x * (size_t)kEW + threadIdx.x; t < n; t += (size_t)gridDim.x * kEW) {
+    const size_t f = t / ((size_t)H * W);
+    const int r = (int)(t - f * H * W);
+    const int y = r / W, x = r - y * W;
+    const double px = x - 0.37 * (double)f, py = y + 0.29 * (double)f;
+    const double k = 6.283185307179586 / 8.0;
+    out[t] = (float)(0.25 * (1.0 + cos(k * px)) * (1.0 + cos(k * py)));
+  }
+}
+
 __global__ void k_add_energy(const double* Ein, double* Eacc, int B, int first) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b < B) Eacc[b] = first ? Ein[b] : Eacc[b] + Ein[b];
@@ -333,6 +347,12 @@ hipError_t launch_adjoint_init(const void* dIa_c, void* dIa, int B, int h, int w
   else
     hipLaunchKernelGGL(k_adjoint_init<float>, dim3(ew_blocks(n)), dim3(kEW), 0, s, (const float*)dIa_c,
                        (float*)dIa, B, h, w);
+  return hipGetLastError();
+}
+
+hipError_t launch_synth_frames(float* out, int F, int H, int W, hipStream_t s) {
+  const size_t n = (size_t)F * H * W;
+  hipLaunchKernelGGL(k_synth_frames, dim3(ew_blocks(n)), dim3(kEW), 0, s, out, F, H, W);
   return hipGetLastError();
 }
 

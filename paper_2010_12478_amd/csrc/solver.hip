@@ -1,6 +1,13 @@
 // Batched registration solver: a persistent kernel fed by a device atomic work
 // queue, and the kernels of the plain one-launch-per-iteration path.
 //
+// Dataflow mode runs a whole series in one launch: a group's leader draws
+// the next slot of a device ready queue; a finished task publishes its output
+// (agent-scope release) and releases each consumer whose last missing input
+// it was.  Groups that finish early draw the next ready registration, wherever
+// it sits in the scan: imbalance between registrations is absorbed across the
+// whole plan, not only within a level.
+//
 // Persistent kernel.  The grid is sized to be fully resident.  Workgroups form
 // groups of g (same blockIdx % 8, so a group shares one XCD and its L2); a
 // group takes registrations from an atomic ticket counter one at a time and
@@ -192,6 +199,26 @@ __device__ bool run_task(const SolveArgs& a, const TaskDesc& d, Group& G, float*
   return true;
 }
 
+// Next task for the calling group's leader.  Batched: the next ticket of the
+// work queue (>= n_tasks: none left).  Dataflow: the next ready-queue slot,
+// waiting until a finished task has filled it (n_tasks once all are drawn).
+__device__ int next_task(const SolveArgs& a, int* queue, int* abort_flag) {
+  if (!a.dataflow) return atomicAdd(queue, 1);
+  const int pos = __hip_atomic_fetch_add(&a.ctrl[2], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (pos >= a.n_tasks) return a.n_tasks;
+  unsigned spins = 0;
+  for (;;) {
+    const int t = ld_relaxed(&a.ready[pos]);
+    if (t >= 0) return t;
+    if (ld_relaxed(abort_flag)) return a.n_tasks;
+    if (++spins > a.spin_limit) {
+      __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return a.n_tasks;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+}
+
 __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) k_persistent(SolveArgs a) {
   __shared__ double red[kWG / kWave];
   __shared__ double s_E;
@@ -218,7 +245,7 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) k
   // are coherent whatever the barrier flavour (the data buffers are not).
   if (threadIdx.x == 0) __hip_atomic_store(&G.xcc[G.member], xcc_id(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (G.member == 0 && threadIdx.x == 0)
-    __hip_atomic_store(&G.task[0], atomicAdd(queue, 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(&G.task[0], next_task(a, queue, abort_flag), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (!group_sync(G, abort_flag, a.spin_limit, &s_flag)) return;   // agent scope: always coherent
   if (G.g > 1) {
     if (threadIdx.x == 0) {
@@ -237,10 +264,29 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) k
     __syncthreads();
     const int t = s_task;
     if (t >= a.n_tasks) break;
+    // dataflow: the inputs were written by other groups, possibly on other
+    // XCDs, and published with an agent-scope release
+    if (a.dataflow) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     if (!run_task(a, a.tasks[t], G, slot, part, par, red, &s_E, &s_flag)) return;
     tpar ^= 1;
+    if (a.dataflow) {
+      // publish this task's output device-wide, then (leader) release its
+      // consumers whose last input it was
+      __threadfence();
+      if (!group_sync(G, abort_flag, a.spin_limit, &s_flag)) return;
+      if (G.member == 0 && threadIdx.x == 0) {
+        for (int q = a.cons_off[t]; q < a.cons_off[t + 1]; ++q) {
+          const int c = a.cons[q];
+          if (__hip_atomic_fetch_add(&a.deps[c], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 1) {
+            const int pos = __hip_atomic_fetch_add(&a.ctrl[3], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&a.ready[pos], c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          }
+        }
+      }
+    }
     if (G.member == 0 && threadIdx.x == 0)
-      __hip_atomic_store(&G.task[tpar], atomicAdd(queue, 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&G.task[tpar], next_task(a, queue, abort_flag), __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
     if (!group_sync(G, abort_flag, a.spin_limit, &s_flag)) return;
   }
 }
@@ -251,6 +297,18 @@ __global__ void k_reset(int* ctrl, int n_ints, const TaskDesc* tasks, int n_task
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_ints; i += gridDim.x * blockDim.x) ctrl[i] = 0;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_tasks; i += gridDim.x * blockDim.x)
     if (tasks[i].status) *tasks[i].status = 4;   // REG_S_ABORTED
+}
+
+__global__ void k_reset_dataflow(int* deps, const int* deps0, int* ready, const int* ready0, int n, int* ctrl,
+                                 int n_ready0) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    deps[i] = deps0[i];
+    ready[i] = ready0[i];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctrl[2] = 0;          // head
+    ctrl[3] = n_ready0;   // tail
+  }
 }
 
 // ---------------------------------------------------------------- plain path
@@ -317,6 +375,13 @@ hipError_t launch_reset_ctrl(int* ctrl, int n_ints, hipStream_t s) {
 hipError_t launch_reset_tasks(int* ctrl, int n_ints, const TaskDesc* tasks, int n_tasks, hipStream_t s) {
   const size_t n = (size_t)(n_ints > n_tasks ? n_ints : n_tasks);
   hipLaunchKernelGGL(k_reset, dim3(grid_for(n)), dim3(256), 0, s, ctrl, n_ints, tasks, n_tasks);
+  return hipGetLastError();
+}
+
+hipError_t launch_reset_dataflow(int* deps, const int* deps0, int* ready, const int* ready0, int n_tasks,
+                                 int* ctrl, int n_ready0, hipStream_t s) {
+  hipLaunchKernelGGL(k_reset_dataflow, dim3(grid_for((size_t)n_tasks)), dim3(256), 0, s, deps, deps0, ready, ready0,
+                     n_tasks, ctrl, n_ready0);
   return hipGetLastError();
 }
 

@@ -22,7 +22,7 @@ TOL_PX = 1e-3
 @pytest.fixture(scope="module")
 def rs():
     import paper_2010_12478_amd as rs
-    rs.set_tuning(32, 16)
+    rs.set_tuning(16, 32)
     return rs
 
 
@@ -86,6 +86,50 @@ def test_plain_and_batched_scan_bitwise(rs):
     b = rs.scan_run(S.frames.cuda(), p, "hier", 3, "lf", mode="batched")
     for x, y in zip(a, b):
         assert torch.equal(x, y)
+
+
+@pytest.mark.parametrize("algo,chunk,glob", [("hier", 3, "lf"), ("dissemination", 0, "lf"), ("seq", 0, "lf"),
+                                             ("bk", 0, "lf"), ("hier", 4, "dissemination")])
+def test_dataflow_matches_level_synchronous_bitwise(rs, algo, chunk, glob):
+    """One launch for the whole series, ops started as their inputs complete,
+    gives exactly the level-by-level result."""
+    announce(f"dataflow {algo} chunk={chunk}")
+    cfg = get_config(2, n_frames=23, height=64, width=96)
+    S = make_series(cfg.series)
+    p = replace(cfg.solver, max_iter=80)
+    a = rs.scan_run(S.frames.cuda(), p, algo, chunk, glob, mode="batched")
+    for mg in (4, 32):
+        rs.set_tuning(16, mg)
+        b = rs.scan_run(S.frames.cuda(), p, algo, chunk, glob, mode="dataflow")
+        for x, y in zip(a, b):
+            assert torch.equal(x, y)
+    rs.set_tuning(16, 32)
+    assert (host(b[3]) & 4 == 0).all()
+
+
+@pytest.mark.parametrize("mode", ["batched", "dataflow"])
+def test_graph_replay_matches_direct_run(rs, mode):
+    """SCAN_F_GRAPH: the first call runs directly and captures the launches;
+    later calls replay the graph.  Every replay, with eager work and
+    synchronisations in between, must equal the direct result bitwise."""
+    announce(f"graph replay {mode}")
+    cfg = get_config(2, n_frames=12, height=64, width=64)
+    S = make_series(cfg.series)
+    p = replace(cfg.solver, max_iter=60)
+    frames = S.frames.cuda()
+    ref = [t.clone() for t in rs.scan_run(frames, p, "hier", 3, "lf", mode=mode)]
+    M = frames.shape[0] - 1
+    n_ops = len(rs.plan(M, "hier", 3, "lf")[0])
+    out = dict(phi0=torch.empty_like(ref[0]), u_pair=torch.empty_like(ref[1]),
+               iters=torch.empty_like(ref[2]), status=torch.empty_like(ref[3]))
+    for rep in range(4):
+        for t in out.values():
+            t.fill_(-7)                      # eager work between replays
+        rs.scan_run(frames, p, "hier", 3, "lf", mode=mode, graph=True, out=out)
+        torch.cuda.synchronize()
+        for want, got in zip(ref, (out["phi0"], out["u_pair"], out["iters"], out["status"])):
+            assert torch.equal(want, got), rep
+    assert out["iters"].shape[0] == M + n_ops
 
 
 def test_two_frames(rs):

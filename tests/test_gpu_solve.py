@@ -159,3 +159,18 @@ def test_invalid_indices_rejected(rs):
     cfg, frames = _series(1, n_frames=3)
     with pytest.raises(rs.RegError):
         rs.solve_batch(frames.cuda(), [0], [7], cfg.solver)
+
+
+def test_autotune_picks_a_candidate_and_keeps_results(rs):
+    announce("autotune 64x64")
+    cfg, frames = _series(2, n_frames=5, height=64, width=64)
+    p = replace(cfg.solver, levels=2, max_iter=40)
+    ref, tmpl = [0, 1, 2, 3], [1, 2, 3, 4]
+    rs.set_tuning(32, 16)
+    base = rs.solve_batch(frames.cuda(), ref, tmpl, p)
+    th, mg = rs.autotune(64, 64, 2, 8)
+    assert th in (16, 32, 64) and mg in (1, 4, 8, 16, 32, 64)
+    assert rs.autotune(64, 64, 2, 8) == (th, mg)          # cached per shape
+    got = rs.solve_batch(frames.cuda(), ref, tmpl, p)
+    for x, y in zip(base, got):
+        assert torch.equal(x, y)
