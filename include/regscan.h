@@ -258,18 +258,28 @@ int scan_run(const float* frames, int N, int H, int W, const reg_params_t* p,
  * number of launches.  HOST outputs; waits for those events. */
 int reg_last_solve_timing(double* total_ms, int* launches);
 
-/* Library tuning: tile height (rows per tile, multiple of 4, 4..64) of the
- * gradient-descent sweep, and the cap on workgroups per registration in
- * batched mode.  0 keeps the current value.  Both are chosen automatically
- * (see reg_autotune) unless set here. */
-int reg_set_tuning(int tile_rows, int max_group);
+/* Library tuning.
+ *   tile_rows  tile height of the finest pyramid level (multiple of 4, 4..64;
+ *              level l uses max(4, tile_rows / 4^l)); it fixes the order in
+ *              which energies are summed, so results depend on it (within
+ *              rounding), not on the other two settings.  Default 32.
+ *   max_group  cap on workgroups per registration in REG_BATCHED and
+ *              REG_DATAFLOW modes (1..128).  Default 32.
+ *   resident   1: pyramid levels whose tiles are 64 columns wide, whose tile
+ *              height is a power of two <= 32 dividing the level height, and
+ *              whose tile count fits the group keep the field in registers
+ *              across iterations (one workgroup per tile); 0: every level
+ *              streams the field through memory.  Default 1.
+ * 0 keeps tile_rows / max_group, -1 keeps resident.  See also reg_autotune. */
+int reg_set_tuning(int tile_rows, int max_group, int resident);
 
 /* Autotuner: on synthetic lattice frames of the given shape, time a batch of
  * `batch` pairwise registrations (REG_BATCHED, 20 fixed iterations per
  * level) for every tile height in {16, 32, 64} and workgroup cap in
- * {1, 4, 8, 16, 32, 64}; keep the fastest as the library tuning and return it
- * (HOST outputs, optional).  Results are cached per shape for the process;
- * outputs of the solver do not depend on the tuning (bitwise). */
+ * {1, 4, 8, 16, 32, 64, 128}; keep the fastest as the library tuning and
+ * return it (HOST outputs, optional).  Results are cached per shape for the
+ * process.  The workgroup cap never changes results; the tile height changes
+ * them only within rounding (the order of the energy sums). */
 int reg_autotune(int H, int W, int levels, int batch, int* tile_rows, int* max_group, void* stream);
 
 /* Free the library workspace and cached graphs. */

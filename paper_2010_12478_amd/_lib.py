@@ -75,7 +75,7 @@ _SIGS = {
     "scan_run": (_I, [_P, _I, _I, _I, ctypes.POINTER(reg_params_t), _I, _I, _I, _I, _I,
                       _P, _P, _P, _P, _P]),
     "reg_last_solve_timing": (_I, [ctypes.POINTER(_D), ctypes.POINTER(_I)]),
-    "reg_set_tuning": (_I, [_I, _I]),
+    "reg_set_tuning": (_I, [_I, _I, _I]),
     "reg_autotune": (_I, [_I, _I, _I, _I, ctypes.POINTER(_I), ctypes.POINTER(_I), _P]),
     "reg_release": (None, []),
 }

@@ -221,8 +221,10 @@ def last_solve_timing():
     return ms.value, n.value
 
 
-def set_tuning(tile_rows=0, max_group=0):
-    check(lib.reg_set_tuning(int(tile_rows), int(max_group)))
+def set_tuning(tile_rows=0, max_group=0, resident=None):
+    """Tile height of the finest level, workgroup cap per registration, and
+    whether levels that fit run register-resident (None keeps it)."""
+    check(lib.reg_set_tuning(int(tile_rows), int(max_group), -1 if resident is None else int(bool(resident))))
 
 
 def autotune(H, W, levels, batch):

@@ -12,7 +12,7 @@ constexpr int kTileW = 64;      // a tile row is one wavefront wide
 constexpr int kMaxLevels = 8;
 constexpr int kRB = 2;          // rows per register batch in the sweep
 
-__host__ __device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+__host__ __device__ inline int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
 
 // Stopping rule of a level (relative energy decrease), shared by the device
 // solver and the host loop of the plain path so both decide identically.
@@ -29,6 +29,12 @@ __device__ __forceinline__ void cell_of(float u, int& c, double& f) {
   fl = fminf(fmaxf(fl, -1048576.f), 1048576.f);   // NaN -> -2^20: taps clamp, value stays NaN
   c = (int)fl;
   f = (double)(u - fl);
+}
+__device__ __forceinline__ void cell_of_f(float u, int& c, float& f) {
+  float fl = floorf(u);
+  fl = fminf(fmaxf(fl, -1048576.f), 1048576.f);
+  c = (int)fl;
+  f = u - fl;
 }
 __device__ __forceinline__ void cell_of(double u, int& c, double& f) {
   float fl = floorf((float)u);
@@ -98,6 +104,13 @@ struct BufView {
   template <typename S>
   __device__ __forceinline__ S load(int i) const {
     if constexpr (sizeof(S) == 4) return f32(i); else return f64(i);
+  }
+  // element v (per lane) + s (wave-uniform, added in the scalar offset)
+  __device__ __forceinline__ float f32(int v, int s) const {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, v * 4, s * 4, AUX));
+  }
+  __device__ __forceinline__ void st32(int v, int s, float x) const {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, x), r, v * 4, s * 4, 0);
   }
 };
 using SharedBuf = BufView<kAuxSC1>;   // data written by other workgroups of the launch

@@ -58,8 +58,9 @@ struct State {
   int device = -1;
   int n_cu = 0;
   int blocks_per_cu = 0;
-  int tile_rows = 16;
+  int tile_rows = 32;
   int max_group = 32;
+  bool resident = true;
   unsigned spin_limit = 1u << 22;   // ~seconds of polling before the watchdog aborts a run
   DevBuf pyr, slots, part, ctrl, tasks, nodes, upair, iters, status, misc, lvl, flow;
   double* h_E = nullptr;   // pinned host scalar for the plain path
@@ -176,8 +177,12 @@ SolveArgs base_args(const float* const lv[kMaxLevels], int H, int W, const reg_p
   a.tau = p->tau;
   a.lam = p->lambda;
   a.rel_tol = p->rel_tol;
-  a.th = g.tile_rows;
-  a.max_tiles = tiles_of(H, W, g.tile_rows);
+  a.max_tiles = 0;
+  for (int l = 0; l < p->levels; ++l) {
+    a.thl[l] = level_tile_rows(g.tile_rows, l);
+    a.max_tiles = std::max(a.max_tiles, tiles_of(H >> l, W >> l, a.thl[l]));
+  }
+  a.resident = g.resident ? 1 : 0;
   a.slot_floats = slot_floats_for(H, W, p->levels, a.lvl_off, &a.bufB_off);
   a.spin_limit = g.spin_limit;
   return a;
@@ -189,14 +194,30 @@ struct Launch {
   int g, groups, grid;
 };
 
-Launch plan_launch(int n_tasks, int H, int W) {
-  const int resident = g.blocks_per_cu * g.n_cu;
-  const int tiles = tiles_of(H, W, g.tile_rows);
+// Workgroups per registration.  When the finest level can run
+// register-resident (64-column tiles, tile height a power of two <= 32 that
+// divides the height) and its tile count fits max_group, the group gets one
+// workgroup per tile.  Otherwise the largest power of two within max_group
+// and the tile count; batched runs stop doubling once fewer groups than tasks
+// would remain.
+int group_size(int n_tasks, int H, int W, bool dataflow) {
+  const int slots = g.blocks_per_cu * g.n_cu;
+  const int th = g.tile_rows;
+  const int tiles = tiles_of(H, W, th);
+  if (g.resident && W % kTileW == 0 && H % th == 0 && th <= 32 && (th & (th - 1)) == 0 &&
+      tiles <= g.max_group && tiles <= kMaxGroup && 8 * tiles <= slots)
+    return tiles;
   int gs = 1;
-  while (gs * 2 <= g.max_group && gs * 2 <= tiles && (long long)n_tasks * gs * 2 <= resident &&
-         8 * gs * 2 <= resident)
+  while (gs * 2 <= g.max_group && gs * 2 <= tiles && 8 * gs * 2 <= slots &&
+         (dataflow || (long long)n_tasks * gs * 2 <= slots))
     gs *= 2;
-  int groups = std::min(resident / gs, ((n_tasks + 7) / 8) * 8);
+  return gs;
+}
+
+Launch plan_launch(int n_tasks, int H, int W) {
+  const int slots = g.blocks_per_cu * g.n_cu;
+  const int gs = group_size(n_tasks, H, W, false);
+  int groups = std::min(slots / gs, ((n_tasks + 7) / 8) * 8);
   groups = std::max(8, (groups / 8) * 8);
   return {gs, groups, groups * gs};
 }
@@ -207,7 +228,8 @@ int run_batched(SolveArgs a, const TaskDesc* d_tasks, int n, hipStream_t s, bool
   const Launch L = plan_launch(n, a.H, a.W);
   const int ctrl_ints = kCtrlHead + kCtrlGroup * L.groups;
   TRY(ensure(g.ctrl, (size_t)ctrl_ints * sizeof(int)));
-  TRY(ensure(g.part, (size_t)L.groups * 2 * a.max_tiles * sizeof(double)));
+  a.max_tiles = std::max(a.max_tiles, L.g);   // resident levels keep one energy slot per member
+  TRY(ensure(g.part, (size_t)L.groups * 3 * a.max_tiles * sizeof(double)));
   TRY(ensure(g.slots, (size_t)L.groups * a.slot_floats * sizeof(float)));
   a.tasks = d_tasks;
   a.n_tasks = n;
@@ -228,14 +250,13 @@ int run_batched(SolveArgs a, const TaskDesc* d_tasks, int n, hipStream_t s, bool
 int run_dataflow(SolveArgs a, const TaskDesc* d_tasks, int n, int* deps, const int* deps0, int* ready,
                  const int* ready0, int n_ready0, const int* cons_off, const int* cons, hipStream_t s, bool timed) {
   if (n == 0) return REG_OK;
-  const int resident = g.blocks_per_cu * g.n_cu;
-  const int tiles = tiles_of(a.H, a.W, g.tile_rows);
-  int gs = 1;
-  while (gs * 2 <= g.max_group && gs * 2 <= tiles && 8 * gs * 2 <= resident) gs *= 2;
-  const int groups = std::max(8, (resident / gs / 8) * 8);
+  const int slots = g.blocks_per_cu * g.n_cu;
+  const int gs = group_size(n, a.H, a.W, true);
+  const int groups = std::max(8, (slots / gs / 8) * 8);
   const int ctrl_ints = kCtrlHead + kCtrlGroup * groups;
   TRY(ensure(g.ctrl, (size_t)ctrl_ints * sizeof(int)));
-  TRY(ensure(g.part, (size_t)groups * 2 * a.max_tiles * sizeof(double)));
+  a.max_tiles = std::max(a.max_tiles, gs);
+  TRY(ensure(g.part, (size_t)groups * 3 * a.max_tiles * sizeof(double)));
   TRY(ensure(g.slots, (size_t)groups * a.slot_floats * sizeof(float)));
   a.tasks = d_tasks;
   a.n_tasks = n;
@@ -286,11 +307,12 @@ int run_plain(SolveArgs a, const std::vector<TaskDesc>& tasks, const TaskDesc* d
       float* other = bufB;
       const float* R = a.pyr[l] + (size_t)d.ref * h * w;
       const float* T = a.pyr[l] + (size_t)d.tmpl * h * w;
-      const int nt = tiles_of(h, w, a.th);
+      const int th = a.thl[l];
+      const int nt = tiles_of(h, w, th);
       double e_prev = 0.0;
       int it = 0;
       for (; it < a.max_iter; ++it) {
-        HIPCHK(launch_plain_sweep(R, T, cur, other, h, w, a.tau, a.lam, a.th, part, s));
+        HIPCHK(launch_plain_sweep(R, T, cur, other, h, w, a.tau, a.lam, th, part, s));
         HIPCHK(launch_plain_reduce(part, nt, dE, s));
         HIPCHK(hipMemcpyAsync(g.h_E, dE, sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
@@ -912,14 +934,16 @@ int reg_last_solve_timing(double* total_ms, int* launches) {
   return REG_OK;
 }
 
-int reg_set_tuning(int tile_rows, int max_group) {
+int reg_set_tuning(int tile_rows, int max_group, int resident) {
   std::lock_guard<std::recursive_mutex> lk(g_mu);
   if (tile_rows != 0 && (tile_rows < 4 || tile_rows > 64 || tile_rows % 4))
     return fail(REG_E_INVALID, "tile_rows %d must be a multiple of 4 in [4, 64]", tile_rows);
-  if (max_group != 0 && (max_group < 1 || max_group > 64 || (max_group & (max_group - 1))))
-    return fail(REG_E_INVALID, "max_group %d must be a power of two in [1, 64]", max_group);
+  if (max_group != 0 && (max_group < 1 || max_group > kMaxGroup))
+    return fail(REG_E_INVALID, "max_group %d must be in [1, %d]", max_group, kMaxGroup);
+  if (resident < -1 || resident > 1) return fail(REG_E_INVALID, "resident %d must be -1, 0 or 1", resident);
   if (tile_rows) g.tile_rows = tile_rows;
   if (max_group) g.max_group = max_group;
+  if (resident >= 0) g.resident = resident != 0;
   return REG_OK;
 }
 
@@ -959,7 +983,7 @@ int reg_autotune(int H, int W, int levels, int batch, int* tile_rows, int* max_g
     int rc = REG_OK;
     for (int th : {16, 32, 64}) {
       if (th > H) continue;
-      for (int mg : {1, 4, 8, 16, 32, 64}) {
+      for (int mg : {1, 4, 8, 16, 32, 64, 128}) {
         g.tile_rows = th;
         g.max_group = mg;
         float ms = 0.f;

@@ -9,8 +9,9 @@ namespace rs {
 
 constexpr int kMaxLevelsHost = 8;
 constexpr int kCtrlHead = 64;     // ints before the per-group control words
-constexpr int kCtrlGroup = 256;   // ints per group: [0..63] member arrival epochs, [64..65] ticket,
-                                  // [128..191] member XCC ids
+constexpr int kMaxGroup = 128;    // workgroups per group at most
+constexpr int kCtrlGroup = 512;   // ints per group: [0..127] member arrival epochs, [128..129] ticket,
+                                  // [256..383] member XCC ids
 
 // One registration of a batch (device array element).
 struct TaskDesc {
@@ -33,10 +34,11 @@ struct SolveArgs {
   const TaskDesc* tasks;
   int n_tasks;
   int g;                 // workgroups per registration (group)
-  int th;                // tile rows
-  int max_tiles;         // partial-sum slots per parity
+  int thl[kMaxLevelsHost];   // tile rows per pyramid level
+  int resident;          // levels that fit the group run register-resident
+  int max_tiles;         // energy slots per buffer (>= tiles of every level, >= g)
   int* ctrl;             // [0] work-queue ticket, [1] abort flag, group q at ctrl + kCtrlHead + kCtrlGroup*q
-  double* part;          // [groups][2][max_tiles]
+  double* part;          // [groups][3][max_tiles]: tile energies / resident energy slots
   float* ws;             // [groups][slot_floats]
   size_t slot_floats;
   size_t lvl_off[kMaxLevelsHost];     // offsets of the pyramid-shaped buffer A per level

@@ -1,0 +1,165 @@
+// Register-resident gradient descent on one pyramid level.
+//
+// A level is cut into tiles of 64 columns by th = 4 * RPT rows; the group's
+// member m owns tile m for the whole level.  Lane = column, wavefront w of the
+// workgroup holds rows y0 .. y0 + RPT - 1 of the tile (y0 = tile row + w*RPT)
+// of the displacement field in registers, so an iteration reads from memory
+// only R and the four taps of T per pixel (through L1/L2) and the halo of its
+// tile, and writes only the tile's halo-facing values:
+//   - rows: every wavefront stores its first and last row, and loads the row
+//     above its first and below its last (rows clamped to the grid: at the
+//     border the neighbour is the pixel itself, so the difference is 0);
+//   - columns: lanes 0 and 63 store their column, and one wave-wide load
+//     fetches the columns left and right of the tile for the wavefront's
+//     rows; a cross-lane permute puts each row's pair into lanes 0 / 63.
+// The field is updated in place, row by row (the old value of the row above
+// is kept aside for the next row).  The state an iteration starts from is
+// copied to LDS first: when the energy of that iteration stops the level, it
+// is the result.  The halo values of iteration t are read from U[t % 2] and
+// those of its result written to U[(t + 1) % 2] (full-size fields of which
+// only halo positions are written), so a reader in iteration t reads what its
+// neighbours wrote before the barrier that ended iteration t - 1, and the
+// writers of iteration t write the other buffer.
+//
+// Per pixel and iteration the arithmetic is pixel_eval and gd_update, the tile
+// energy is summed in the order of the streaming sweep with the same tile
+// height (per lane over its rows, the butterfly, the 4 wavefronts), so both
+// paths produce bitwise identical fields, energies and iteration counts.
+#pragma once
+
+#include "sweep.h"
+
+namespace rs {
+
+// Whole-wavefront lane shifts by one (DPP wave_shr:1 / wave_shl:1): lane i
+// receives src from lane i - 1 (from_left) or i + 1 (from_right); the lane
+// without a source (0, respectively 63) keeps `edge`.
+__device__ __forceinline__ float from_left(float src, float edge) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, edge),
+                                                               __builtin_bit_cast(int, src), 0x138, 0xf, 0xf,
+                                                               false));
+}
+__device__ __forceinline__ float from_right(float src, float edge) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, edge),
+                                                               __builtin_bit_cast(int, src), 0x130, 0xf, 0xf,
+                                                               false));
+}
+
+// Value of `v` in lane `src_lane` (per lane), through the LDS crossbar.
+__device__ __forceinline__ float lane_pull(float v, int src_lane) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(src_lane << 2, __builtin_bit_cast(int, v)));
+}
+
+constexpr int kMaxRPT = 8;   // rows per thread at most (tile height 32)
+
+struct ResidentTile {
+  int h, w, hw;
+  int xt, y0;        // the tile's first column, the wavefront's first row
+  int lane;
+  double tau, lam;
+};
+
+// One iteration on the state (sx, sy), updated in place (R and T read
+// through rb and tb): returns this lane's energy sum over its rows (in row
+// order).  `ucur` holds the halo of the state; the halo-facing values of the
+// new state are stored through `unext`; the old state is saved to `roll`
+// (RPT float2 per thread, LDS).
+template <int RPT>
+__device__ __forceinline__ double resident_step(const ResidentTile& P, float (&sx)[RPT], float (&sy)[RPT],
+                                                const SharedBuf& ucur, const ReadBuf& unext, const ReadBuf& tb,
+                                                const ReadBuf& rb, float2* roll) {
+  // P.h, P.w, P.xt, P.y0 are wave-uniform: row offsets go to the scalar
+  // offset of the buffer instructions, the per-lane offset is the lane
+  const int h = P.h, w = P.w, hw = P.hw, y0 = P.y0, xt = P.xt;
+  // per-lane values derived afresh every iteration rather than held in
+  // registers across the level (the empty asm hides their invariance)
+  int lane = P.lane;
+  asm volatile("" : "+v"(lane));
+  const int x = xt + lane;
+  // halo loads
+  const int ru = __mul24(max(y0 - 1, 0), w) + xt, rd = __mul24(min(y0 + RPT, h - 1), w) + xt;
+  const float hux = ucur.f32(lane, ru), huy = ucur.f32(lane, hw + ru);
+  const float hdx = ucur.f32(lane, rd), hdy = ucur.f32(lane, hw + rd);
+  // lane k < 4 RPT: side k / (2 RPT) (0 left, 1 right), component (k / RPT) & 1, row k % RPT
+  const int k = lane & (4 * RPT - 1);
+  const int side = k / (2 * RPT), comp = (k / RPT) & 1, rk = k & (RPT - 1);
+  const int col = side ? min(xt + kTileW, w - 1) : max(xt - 1, 0);
+  const float hcol = ucur.f32(comp * hw + __mul24(rk, w) + col, __mul24(y0, w));
+  const int sel = lane == kWave - 1 ? 2 * RPT : 0;   // lane 63 pulls the right column, the others the left
+
+  // the state this iteration starts from
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) roll[r * kWG] = make_float2(sx[r], sy[r]);
+
+  // Rows are computed in order; R and the four taps of T for row r + kAhead
+  // are loaded while row r is computed (scheduling barriers keep each row's
+  // work in its own block, which bounds the registers in flight).
+  constexpr int kAhead = RPT < 2 ? RPT : 2;
+  float taps[RPT][4];
+  float fxs[RPT], fys[RPT], rr[RPT];
+  auto gather = [&](int r) {
+    rr[r] = rb.f32(lane, __mul24(y0 + r, w) + xt);
+    int ix, iy;
+    cell_of_f(sx[r], ix, fxs[r]);
+    cell_of_f(sy[r], iy, fys[r]);
+    const int xa = clampi(x + ix, 0, w - 1), xb = clampi(x + ix + 1, 0, w - 1);
+    const int ya = __mul24(clampi(y0 + r + iy, 0, h - 1), w), yb = __mul24(clampi(y0 + r + iy + 1, 0, h - 1), w);
+    taps[r][0] = tb.f32(ya + xa);
+    taps[r][1] = tb.f32(ya + xb);
+    taps[r][2] = tb.f32(yb + xa);
+    taps[r][3] = tb.f32(yb + xb);
+  };
+#pragma unroll
+  for (int r = 0; r < kAhead; ++r) gather(r);
+  __builtin_amdgcn_sched_barrier(0);
+
+  double acc = 0.0;
+  float upx = hux, upy = huy;   // old value of the row above
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    if (r + kAhead < RPT) gather(r + kAhead);
+    const float ex = lane_pull(hcol, sel + r), ey = lane_pull(hcol, sel + RPT + r);
+    const float lx = from_left(sx[r], ex), ly = from_left(sy[r], ey);
+    const float rx = from_right(sx[r], ex), ry = from_right(sy[r], ey);
+    const float dx = r == RPT - 1 ? hdx : sx[r + 1], dy = r == RPT - 1 ? hdy : sy[r + 1];
+    const float cxs = sx[r], cys = sy[r];
+    const double cx = cxs, cy = cys;
+    double e, gx, gy;
+    pixel_eval(fxs[r], fys[r], taps[r][0], taps[r][1], taps[r][2], taps[r][3], rr[r], cx, cy, lx, ly, rx, ry,
+               upx, upy, dx, dy, P.lam, e, gx, gy);
+    acc += e;
+    sx[r] = gd_update<float>(cx, gx, P.tau);
+    sy[r] = gd_update<float>(cy, gy, P.tau);
+    // pin the row's results here: without this the compiler sinks the
+    // energy and update arithmetic of all rows to the end of the iteration,
+    // keeping every row's intermediates live at once
+    asm volatile("" : "+v"(acc), "+v"(sx[r]), "+v"(sy[r]));
+    upx = cxs;
+    upy = cys;
+    __builtin_amdgcn_sched_barrier(0);
+  }
+
+  // halo-facing values of the new state: the first and last rows, and (lanes
+  // 0 and 63) the tile's first and last columns
+  {
+    const int o = __mul24(y0, w) + xt;
+    unext.st32(lane, o, sx[0]);
+    unext.st32(lane, hw + o, sy[0]);
+    if (RPT > 1) {
+      const int q = __mul24(y0 + RPT - 1, w) + xt;
+      unext.st32(lane, q, sx[RPT - 1]);
+      unext.st32(lane, hw + q, sy[RPT - 1]);
+    }
+    if (RPT > 2 && (lane == 0 || lane == kWave - 1)) {
+#pragma unroll
+      for (int r = 1; r < RPT - 1; ++r) {
+        const int q = __mul24(y0 + r, w) + xt;
+        unext.st32(lane, q, sx[r]);
+        unext.st32(lane, hw + q, sy[r]);
+      }
+    }
+  }
+  return acc;
+}
+
+}  // namespace rs

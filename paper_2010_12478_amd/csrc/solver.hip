@@ -23,6 +23,7 @@
 // by the canonical wave sum over tiles, so the plain path, the persistent
 // kernel at any group size, and repeated runs agree bitwise.
 #include "internal.h"
+#include "resident.h"
 #include "sweep.h"
 
 namespace rs {
@@ -77,9 +78,11 @@ __device__ bool group_sync(Group& G, int* abort_flag, unsigned spin_limit, int* 
     int ok = 1;
     unsigned spins = 0;
     for (;;) {
-      const int v = lane < G.g ? ld_relaxed(&G.arrive[lane]) : G.epoch;
-      if (__all(v >= G.epoch)) break;
-      if (ld_relaxed(abort_flag)) {
+      const int v0 = lane < G.g ? ld_relaxed(&G.arrive[lane]) : G.epoch;
+      const int v1 = lane + kWave < G.g ? ld_relaxed(&G.arrive[lane + kWave]) : G.epoch;
+      const int abort = ld_relaxed(abort_flag);   // in the same round trip
+      if (__all(min(v0, v1) >= G.epoch)) break;
+      if (abort) {
         ok = 0;
         break;
       }
@@ -97,13 +100,171 @@ __device__ bool group_sync(Group& G, int* abort_flag, unsigned spin_limit, int* 
   return *s_flag != 0;
 }
 
+// Barrier of the resident loop that also carries the energies.  Member m
+// publishes its tile energy (0 for idle members) in slot m of the
+// iteration's buffer, once the stores of all its wavefronts to shared data
+// are complete; its wavefront 0 waits until all g slots are filled and forms
+// the level energy in the canonical order (the tiles 0 .. nt-1 summed as in
+// wave_sum_array), which it passes to the other wavefronts through LDS.
+//
+// The slots rotate over three buffers.  At the start of iteration t a member
+// empties its slot of buffer (t + 1) % 3, last filled in t - 2 and read by
+// every member before it published in t - 1 (which this member has seen);
+// that store completes before the member publishes in t, so no member polling
+// in t + 1 can mistake the value of t - 2 for a new one.
+constexpr unsigned long long kSlotEmpty = ~0ull;   // a NaN no arithmetic produces
+
+// Called by all threads with this thread's energy sum `acc`; returns false
+// if the run was aborted, otherwise E is the level energy.
+__device__ bool energy_barrier(const Group& G, unsigned long long* cur, double acc, bool active, int nt,
+                               int* abort_flag, unsigned spin_limit, double* red, double* s_E, int* s_flag,
+                               double& E) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const double wp = wave_sum(acc);
+  if (G.local)
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  else
+    __threadfence();
+  if (lane == 0) red[threadIdx.x >> 6] = wp;
+  __syncthreads();
+  if (threadIdx.x < kWave) {
+    if (lane == 0) {
+      double t = 0.0;   // the order of block_sum
+#pragma unroll
+      for (int w = 0; w < kWG / kWave; ++w) t += red[w];
+      __hip_atomic_store(cur + G.member, __builtin_bit_cast(unsigned long long, active ? t : 0.0),
+                         G.local ? __ATOMIC_RELAXED : __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    const bool t0 = lane < G.g, t1 = lane + kWave < G.g;
+    unsigned long long v0, v1;
+    int ok = 1;
+    unsigned spins = 0;
+    for (;;) {
+      v0 = t0 ? __hip_atomic_load(cur + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0ull;
+      v1 = t1 ? __hip_atomic_load(cur + lane + kWave, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0ull;
+      const int abort = ld_relaxed(abort_flag);   // in the same round trip
+      if (__all(v0 != kSlotEmpty && v1 != kSlotEmpty)) break;
+      if (abort) {
+        ok = 0;
+        break;
+      }
+      if (++spins > spin_limit) {
+        if (lane == 0) __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    double sum = 0.0;
+    if (lane < nt) sum += __builtin_bit_cast(double, v0);
+    if (lane + kWave < nt) sum += __builtin_bit_cast(double, v1);
+    sum = wave_sum(sum);
+    if (lane == 0) {
+      *s_E = sum;
+      *s_flag = ok;
+    }
+  }
+  __syncthreads();
+  if (!G.local) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  E = *s_E;
+  return *s_flag != 0;
+}
+
+// One pyramid level with the field resident in registers (see resident.h):
+// member m owns tile m (members beyond the tile count only take part in the
+// barriers).  U0 holds the level's initial field and receives its result
+// (whole); U1 is the second halo buffer; roll is the LDS copy of the state an
+// iteration starts from (kWG * RPT float2).  Returns false on abort;
+// otherwise `iters` is the number of updates kept and `nonfinite` tells
+// whether an energy was not finite (then U0 is left as it is).
+template <int RPT>
+__device__ bool level_resident(const SolveArgs& a, const LevelView<float>& V, float* U0, float* U1, Group& G,
+                               double* part, int& par, double* red, double* s_E, int* s_flag, float2* roll,
+                               int& iters, bool& nonfinite) {
+  int* abort_flag = a.ctrl + 1;
+  constexpr int th = 4 * RPT;
+  const int h = V.h, w = V.w;
+  const int ntx = w / kTileW;
+  const int nt = ntx * (h / th);
+  const bool active = G.member < nt;
+  const int tile = active ? G.member : 0;
+  ResidentTile P;
+  P.h = h;
+  P.w = w;
+  P.hw = h * w;
+  P.lane = threadIdx.x & (kWave - 1);
+  P.xt = (tile % ntx) * kTileW;
+  P.y0 = (tile / ntx) * th + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * RPT;
+  P.tau = V.tau;
+  P.lam = V.lam;
+  const ReadBuf tb(V.T), rb(V.R);
+  float sx[RPT], sy[RPT];
+  {
+    const SharedBuf u0(U0);
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      const int o = __mul24(P.y0 + r, w) + P.xt + P.lane;
+      sx[r] = active ? u0.f32(o) : 0.f;
+      sy[r] = active ? u0.f32(P.hw + o) : 0.f;
+    }
+  }
+  roll += threadIdx.x;
+  // energy slots: three buffers of a.max_tiles (>= g) words, this member's
+  // emptied before the first iteration
+  unsigned long long* slots = (unsigned long long*)part;
+  const size_t sbuf = (size_t)a.max_tiles;
+  if (threadIdx.x < 3) slots[threadIdx.x * sbuf + G.member] = kSlotEmpty;
+  if (!group_sync(G, abort_flag, a.spin_limit, s_flag)) return false;
+  double e_prev = 0.0;
+  int it = 0, slot = 0;
+  bool rollback = false;
+  nonfinite = false;
+  for (; it < a.max_iter; ++it) {
+    const int nslot = slot == 2 ? 0 : slot + 1;
+    if (threadIdx.x == 0)
+      __hip_atomic_store(slots + nslot * sbuf + G.member, kSlotEmpty, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const bool odd = it & 1;
+    const SharedBuf ucur(odd ? U1 : U0);
+    const ReadBuf unext(odd ? U0 : U1);
+    const double acc = active ? resident_step<RPT>(P, sx, sy, ucur, unext, tb, rb, roll) : 0.0;
+    double E;
+    if (!energy_barrier(G, slots + slot * sbuf, acc, active, nt, abort_flag, a.spin_limit, red, s_E, s_flag, E))
+      return false;
+    slot = nslot;
+    if (!isfinite(E)) {
+      nonfinite = true;
+      break;
+    }
+    if (!a.fixed_iter && it > 0 && level_stops(e_prev, E, a.rel_tol)) {
+      rollback = true;
+      break;
+    }
+    e_prev = E;
+  }
+  iters = it;
+  if (!nonfinite && active) {
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      if (rollback) {
+        const float2 v = roll[r * kWG];
+        sx[r] = v.x;
+        sy[r] = v.y;
+      }
+      const int o = __mul24(P.y0 + r, w) + P.xt + P.lane;
+      U0[o] = sx[r];
+      U0[P.hw + o] = sy[r];
+    }
+  }
+  return true;
+}
+
 __device__ __forceinline__ float* start_buffer(const SolveArgs& a, const TaskDesc& d, float* slot, int l) {
   return l == 0 ? d.out : slot + a.lvl_off[l];
 }
 
 // Runs one registration with the calling group.  Returns false on abort.
 __device__ bool run_task(const SolveArgs& a, const TaskDesc& d, Group& G, float* slot, double* part, int& par,
-                         double* red, double* s_E, int* s_flag) {
+                         double* red, double* s_E, int* s_flag, float2* roll) {
   int* abort_flag = a.ctrl + 1;
   const int L = a.levels;
   const int stride = G.g * kWG;
@@ -145,7 +306,6 @@ __device__ bool run_task(const SolveArgs& a, const TaskDesc& d, Group& G, float*
       if (!group_sync(G, abort_flag, a.spin_limit, s_flag)) return false;
       cur = dst;
     }
-    float* other = bufB;
     LevelView<float> V;
     V.R = a.pyr[l] + (size_t)d.ref * n;
     V.T = a.pyr[l] + (size_t)d.tmpl * n;
@@ -153,14 +313,34 @@ __device__ bool run_task(const SolveArgs& a, const TaskDesc& d, Group& G, float*
     V.w = w;
     V.tau = a.tau;
     V.lam = a.lam;
-    const int nt = tiles_of(h, w, a.th);
+    const int th = a.thl[l];
+    const int nt = tiles_of(h, w, th);
+    if (a.resident && w % kTileW == 0 && h % th == 0 && nt <= G.g && th <= 32 && (th & (th - 1)) == 0) {
+      int it = 0;
+      bool nf = false, ok = true;
+      if (th == 4) ok = level_resident<1>(a, V, cur, bufB, G, part, par, red, s_E, s_flag, roll, it, nf);
+      else if (th == 8) ok = level_resident<2>(a, V, cur, bufB, G, part, par, red, s_E, s_flag, roll, it, nf);
+      else if (th == 16) ok = level_resident<4>(a, V, cur, bufB, G, part, par, red, s_E, s_flag, roll, it, nf);
+      else ok = level_resident<8>(a, V, cur, bufB, G, part, par, red, s_E, s_flag, roll, it, nf);
+      if (!ok) return false;
+      iters[l] = it;
+      if (nf) {
+        status |= 2;   // REG_S_NONFINITE
+        dead = true;
+      } else if (!group_sync(G, abort_flag, a.spin_limit, s_flag)) {   // the result is read whole next
+        return false;
+      }
+      if (it == a.max_iter && !a.fixed_iter) status |= 1;   // REG_S_MAXITER
+      continue;
+    }
+    float* other = bufB;
     double e_prev = 0.0;
     int it = 0;
     for (; it < a.max_iter; ++it) {
       V.u = cur;
       V.out = other;
       double* pp = part + (size_t)par * a.max_tiles;
-      sweep_tiles<float, SW_UPDATE, false>(V, G.member, G.g, a.th, red, pp, nullptr);
+      sweep_tiles<float, SW_UPDATE, false>(V, G.member, G.g, th, red, pp, nullptr);
       if (!group_sync(G, abort_flag, a.spin_limit, s_flag)) return false;
       if (threadIdx.x < kWave) {
         const double E = wave_sum_array(pp, nt, threadIdx.x);
@@ -224,6 +404,7 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) k
   __shared__ double s_E;
   __shared__ int s_flag;
   __shared__ int s_task;
+  __shared__ float2 roll[kWG * kMaxRPT];
   const int xcd = blockIdx.x & 7, lb = blockIdx.x >> 3;
   Group G;
   G.g = a.g;
@@ -231,13 +412,13 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) k
   G.id = (lb / a.g) * 8 + xcd;
   int* gctl = a.ctrl + kCtrlHead + kCtrlGroup * G.id;
   G.arrive = gctl;
-  G.task = gctl + 64;
-  G.xcc = gctl + 128;
+  G.task = gctl + kMaxGroup;
+  G.xcc = gctl + 2 * kMaxGroup;
   G.epoch = 0;
   G.local = false;
   int* queue = a.ctrl;
   int* abort_flag = a.ctrl + 1;
-  double* part = a.part + (size_t)G.id * 2 * a.max_tiles;
+  double* part = a.part + (size_t)G.id * 3 * a.max_tiles;
   float* slot = a.ws + (size_t)G.id * a.slot_floats;
   int par = 0, tpar = 0;
 
@@ -267,7 +448,7 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) k
     // dataflow: the inputs were written by other groups, possibly on other
     // XCDs, and published with an agent-scope release
     if (a.dataflow) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    if (!run_task(a, a.tasks[t], G, slot, part, par, red, &s_E, &s_flag)) return;
+    if (!run_task(a, a.tasks[t], G, slot, part, par, red, &s_E, &s_flag, roll)) return;
     tpar ^= 1;
     if (a.dataflow) {
       // publish this task's output device-wide, then (leader) release its

@@ -42,6 +42,49 @@ struct LevelView {
 __host__ __device__ inline int tiles_x(int w) { return (w + kTileW - 1) / kTileW; }
 __host__ __device__ inline int tiles_of(int h, int w, int th) { return tiles_x(w) * ((h + th - 1) / th); }
 
+// Tile height of pyramid level l for a finest-level tile height th0: a
+// quarter per level (both sides halve), at least 4 rows, so that every level
+// of a square image has about as many tiles as the finest one.
+__host__ __device__ inline int level_tile_rows(int th0, int l) {
+  const int t = th0 >> (2 * l);
+  return t < 4 ? 4 : t;
+}
+
+// One pixel of the fused sweep, everything in double: bilinear sample S of T
+// from the taps i00 (x0, y0), i01 (x0 + 1, y0), i10 (x0, y0 + 1), i11 at the
+// in-cell fractions (fx, fy), with its position derivatives; residual
+// r = S - R; the neighbour values (c = pixel, l/r/u/d = left/right/up/down,
+// the pixel itself where the neighbour lies outside the grid).
+//   e  = r^2 + lam * ((rx - cx)^2 + (dx - cx)^2 + (ry - cy)^2 + (dy - cy)^2)
+//   g  = 2 r dS/dp + 2 lam * sum over the 4 neighbours of (c - n)
+// Every execution path evaluates a pixel through this function, so they agree
+// bitwise.
+__device__ __forceinline__ void pixel_eval(double fx, double fy, double i00, double i01, double i10, double i11,
+                                           double R, double cx, double cy, double lx, double ly, double rx,
+                                           double ry, double ux, double uy, double dx, double dy, double lam,
+                                           double& e, double& gx, double& gy) {
+  const double a = i01 - i00, b = i11 - i10, c = i10 - i00, d = i11 - i01;
+  const double top = fma(fx, a, i00), bot = fma(fx, b, i10);
+  const double s = fma(fy, bot - top, top);
+  const double sx = fma(fy, b - a, a);
+  const double sy = fma(fx, d - c, c);
+  const double res = s - R;
+  const double hx = rx - cx, vx = dx - cx, hy = ry - cy, vy = dy - cy;
+  const double nbx = ((cx - lx) - hx) + ((cx - ux) - vx);
+  const double nby = ((cy - ly) - hy) + ((cy - uy) - vy);
+  const double reg = fma(hx, hx, vx * vx) + fma(hy, hy, vy * vy);
+  e = fma(res, res, lam * reg);
+  const double r2 = res + res, l2 = lam + lam;
+  gx = fma(r2, sx, l2 * nbx);
+  gy = fma(r2, sy, l2 * nby);
+}
+
+// Gradient-descent update of one component, rounded once to the stored type.
+template <typename S>
+__device__ __forceinline__ S gd_update(double c, double g, double tau) {
+  return (S)fma(-tau, g, c);
+}
+
 // Registers of one unit of work of a wavefront: rows [yb, ye) (at most kRB)
 // of one tile, lane = column.
 template <typename S>
@@ -173,29 +216,16 @@ __device__ void sweep_tiles(const LevelView<S>& L, int first, int stride, int th
           rxs = A.hx[r];
           rys = A.hy[r];
         }
-        const double fx = fxs[r], fy = fys[r];
-        const double i00 = taps[r][0], i01 = taps[r][1], i10 = taps[r][2], i11 = taps[r][3];
-        const double ox = 1.0 - fx, oy = 1.0 - fy;
-        const double s = oy * (ox * i00 + fx * i01) + fy * (ox * i10 + fx * i11);
-        const double dsx = oy * (i01 - i00) + fy * (i11 - i10);
-        const double dsy = ox * (i10 - i00) + fx * (i11 - i01);
         const double cx = cxs, cy = cys;
-        const double lx = lxs, ly = lys, rx = rxs, ry = rys;
-        const double upx = A.ax[r], upy = A.ay[r], dnx = A.ax[r + 2], dny = A.ay[r + 2];
-        const double res = s - (double)A.rr[r];
-        const double drx = rx - cx, dry = ry - cy;
-        const double ddx = dnx - cx, ddy = dny - cy;
-        const double e = res * res + lam * ((drx * drx + ddx * ddx) + (dry * dry + ddy * ddy));
-        const double nbx = ((cx - lx) + (cx - rx)) + ((cx - upx) + (cx - dnx));
-        const double nby = ((cy - ly) + (cy - ry)) + ((cy - upy) + (cy - dny));
-        const double gx = 2.0 * res * dsx + 2.0 * lam * nbx;
-        const double gy = 2.0 * res * dsy + 2.0 * lam * nby;
+        double e, gx, gy;
+        pixel_eval(fxs[r], fys[r], taps[r][0], taps[r][1], taps[r][2], taps[r][3], A.rr[r], cx, cy, lxs, lys,
+                   rxs, rys, A.ax[r], A.ay[r], A.ax[r + 2], A.ay[r + 2], lam, e, gx, gy);
         if (vx) {
           accE += e;
           const int o = __mul24(y, w) + x;
           if (WRITE == SW_UPDATE) {
-            L.out[o] = (S)(cx - tau * gx);
-            L.out[hw + o] = (S)(cy - tau * gy);
+            L.out[o] = gd_update<S>(cx, gx, tau);
+            L.out[hw + o] = gd_update<S>(cy, gy, tau);
           } else if (WRITE == SW_GRAD) {
             L.out[o] = (S)gx;
             L.out[hw + o] = (S)gy;

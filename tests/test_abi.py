@@ -97,5 +97,6 @@ def test_invalid_arguments_rejected_before_any_gpu_use(rs):
     rc = lib.scan_run(ctypes.c_void_p(16), 1, 16, 16, ctypes.byref(p), 0, 0, 0, 1, 0,
                       ctypes.c_void_p(16), None, None, None, None)
     assert rc == -1
-    assert lib.reg_set_tuning(6, 0) == -1
-    assert lib.reg_set_tuning(0, 3) == -1
+    assert lib.reg_set_tuning(6, 0, -1) == -1
+    assert lib.reg_set_tuning(0, 129, -1) == -1
+    assert lib.reg_set_tuning(0, 0, 2) == -1

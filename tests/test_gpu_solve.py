@@ -25,9 +25,9 @@ def rs():
 
 @pytest.fixture(autouse=True)
 def _default_tuning(rs):
-    rs.set_tuning(32, 16)
+    rs.set_tuning(32, 16, resident=True)
     yield
-    rs.set_tuning(32, 16)
+    rs.set_tuning(32, 16, resident=True)
 
 
 def _series(index, **kw):
@@ -111,6 +111,49 @@ def test_tile_rows_match_oracle(rs, tile_rows):
         assert np.abs(host(u)[b] - w.u).max() <= TOL_PX
 
 
+@pytest.mark.parametrize("tile_rows", [4, 8, 16, 32])
+@pytest.mark.parametrize("H,W,levels", [(64, 64, 1), (128, 192, 2), (256, 128, 3)])
+def test_resident_levels_match_streaming_bitwise(rs, tile_rows, H, W, levels):
+    """Register-resident levels (one workgroup per tile) give the same bits
+    as the streaming sweep with the same tiles, and match the oracle."""
+    announce(f"resident vs streaming {H}x{W} L={levels} th={tile_rows}")
+    cfg, frames = _series(2, n_frames=4, height=H, width=W)
+    p = replace(cfg.solver, levels=levels, max_iter=60)
+    ref, tmpl = [0, 1, 2], [1, 2, 3]
+    rs.set_tuning(tile_rows, 128, resident=False)
+    a = rs.solve_batch(frames.cuda(), ref, tmpl, p)
+    rs.set_tuning(tile_rows, 128, resident=True)
+    b = rs.solve_batch(frames.cuda(), ref, tmpl, p)
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+    if tile_rows == 32:
+        want = _oracle_batch(frames, ref, tmpl, p)
+        for k, w in enumerate(want):
+            assert np.abs(host(b[0])[k] - w.u).max() <= TOL_PX
+            assert host(b[1])[k].tolist() == list(w.iters)
+
+
+def test_resident_stop_keeps_previous_state_and_nonfinite(rs):
+    """A level that stops on the energy test returns the state its last
+    iteration started from (the LDS copy); a non-finite frame still flags the
+    registration and fills it with NaN."""
+    announce("resident stop/nonfinite")
+    cfg, frames = _series(2, n_frames=4, height=128, width=128)
+    frames = frames.clone()
+    frames[3, 5, 70] = float("inf")
+    p = replace(cfg.solver, levels=2, max_iter=150)
+    rs.set_tuning(32, 16, resident=True)
+    u, iters, status = rs.solve_batch(frames.cuda(), [0, 1, 2], [1, 2, 3], p)
+    want = _oracle_batch(frames, [0, 1, 2], [1, 2, 3], p)
+    st = host(status)
+    for k in range(2):
+        assert np.abs(host(u)[k] - want[k].u).max() <= TOL_PX
+        assert host(iters)[k].tolist() == list(want[k].iters)
+        assert st[k] == want[k].status
+    assert st[2] & 2 and want[2].status & 2
+    assert torch.isnan(u[2]).all()
+
+
 def test_given_initial_guess(rs):
     announce("solve with u0")
     cfg, frames = _series(2, n_frames=3, height=64, width=64)
@@ -166,11 +209,11 @@ def test_autotune_picks_a_candidate_and_keeps_results(rs):
     cfg, frames = _series(2, n_frames=5, height=64, width=64)
     p = replace(cfg.solver, levels=2, max_iter=40)
     ref, tmpl = [0, 1, 2, 3], [1, 2, 3, 4]
-    rs.set_tuning(32, 16)
-    base = rs.solve_batch(frames.cuda(), ref, tmpl, p)
     th, mg = rs.autotune(64, 64, 2, 8)
-    assert th in (16, 32, 64) and mg in (1, 4, 8, 16, 32, 64)
+    assert th in (16, 32, 64) and mg in (1, 4, 8, 16, 32, 64, 128)
     assert rs.autotune(64, 64, 2, 8) == (th, mg)          # cached per shape
-    got = rs.solve_batch(frames.cuda(), ref, tmpl, p)
-    for x, y in zip(base, got):
-        assert torch.equal(x, y)
+    u, iters, status = rs.solve_batch(frames.cuda(), ref, tmpl, p)
+    want = _oracle_batch(frames, ref, tmpl, p)
+    for b, w in enumerate(want):
+        assert np.abs(host(u)[b] - w.u).max() <= TOL_PX
+        assert host(iters)[b].tolist() == list(w.iters)
