@@ -2,21 +2,25 @@
 
 Workload: 256 synthetic 256x256 lattice frames (drift <= 4 px, noise 0.1), a
 2-level pyramid, relative-decrease stopping (1e-5, at most 200 iterations per
-level), the hierarchical reduce-then-scan plan (chunks of 16 elements,
+level), the hierarchical reduce-then-scan plan (chunks of 4 elements,
 Ladner-Fischer global phase).  One step = frame pyramid + the 255 pairwise
-registrations + every scan level, all through scan_run in batched mode
-(one persistent launch per scan level), inputs resident in HBM.
+registrations + every scan level through scan_run in batched mode: one
+persistent launch for the pairwise phase and one per scan level, the whole
+schedule replayed from a captured hipGraph; inputs resident in HBM.
 
-Prints one JSON line with frames registered per second, the roofline of the
-dominant kernel (the persistent gradient-descent solver) from HIP events
-recorded by the library around each of its launches, the plain
-one-launch-per-iteration path on the same GPU, and the CPU oracle timed on a
-bounded sample on the host cores.
+Prints one JSON line: frames registered per second over the K timed steps
+(with the per-step times and their 95% confidence interval, and the split
+between the pairwise phase and the scan levels from HIP events the library
+records around each persistent launch); the roofline of the dominant kernel
+(the persistent gradient-descent solver, same events); the dataflow mode
+(whole scan in one launch) and the plain one-launch-per-iteration path on
+the same GPU; and the CPU oracle timed on a bounded sample on the host cores.
 """
 from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -29,17 +33,35 @@ PEAK_HBM_GBS = 8000.0
 SWEEP_BYTES = 24      # per pixel and kept update: R 4 + T 4 + u 8 read, u' 8 written
 EVAL_BYTES = 16       # per pixel of the final evaluation sweep (no update kept)
 FIELD_BYTES = 8       # one float32 displacement vector
+TILE_ROWS, MAX_GROUP = 64, 64   # the library defaults, set explicitly
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-dataflow", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=0, help="registrations in the oracle sample")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run 3 device-to-device copies of MIB MiB (calibrates the HBM byte counters)")
     return ap.parse_args()
+
+
+def copy_probe(mib):
+    """A plain copy kernel of known size: what FETCH_SIZE / WRITE_SIZE read
+    for it scales the counters of the solver to bytes."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.rand(n, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": n * 4, "copies": 3}), flush=True)
 
 
 def algorithmic_bytes(iters, n_pair, H, W, levels, max_iter):
@@ -64,6 +86,17 @@ def algorithmic_bytes(iters, n_pair, H, W, levels, max_iter):
     return total
 
 
+def ci95(xs):
+    """Half-width of the 95% confidence interval of the mean (Student t)."""
+    n = len(xs)
+    if n < 2:
+        return None
+    from scipy.stats import t
+    m = sum(xs) / n
+    sd = math.sqrt(sum((x - m) ** 2 for x in xs) / (n - 1))
+    return float(t.ppf(0.975, n - 1) * sd / math.sqrt(n))
+
+
 def cpu_baseline(cfg, frames_cpu, n_total_regs, sample):
     """Oracle throughput on the host cores: `sample` pairwise registrations of
     the workload spread over one worker process per core, scaled to frames/s
@@ -71,8 +104,6 @@ def cpu_baseline(cfg, frames_cpu, n_total_regs, sample):
     cores (which favours the oracle: the scan's dependencies are ignored)."""
     import multiprocessing as mp
     from concurrent.futures import ProcessPoolExecutor
-
-    from oracle.registration import pyramid, register
 
     cores = min(len(os.sched_getaffinity(0)), 16)
     sample = sample or 4 * cores
@@ -102,12 +133,14 @@ def _oracle_pair(a):
 
 def main():
     args = parse()
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the scan shards across GPUs "
               "by its reduce-then-scan hierarchy, which is not built here.", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     from synth import get_config, make_series
@@ -139,28 +172,36 @@ def main():
                u_pair=torch.empty((M, 2, H, W), device=dev),
                iters=torch.empty((n_regs, p.levels), dtype=torch.int32, device=dev),
                status=torch.empty(n_regs, dtype=torch.int32, device=dev))
+    rs.set_tuning(TILE_ROWS, MAX_GROUP, resident=True)
 
-    def step():
-        rs.scan_run(frames, p, cfg.algo, cfg.chunk, cfg.global_algo, mode="batched", out=out)
+    def step(mode="batched", graph=True):
+        rs.scan_run(frames, p, cfg.algo, cfg.chunk, cfg.global_algo, mode=mode, graph=graph, out=out)
 
-    for _ in range(args.warmup):
+    for _ in range(args.warmup):     # the first call also captures the graph
         step()
     torch.cuda.synchronize()
-    kern_ms, kern_launches, alg_bytes = 0.0, 0, 0
+    step_ms, pair_ms, scan_ms, kern_ms, kern_launches = [], [], [], 0.0, 0
     t0 = time.perf_counter()
     for _ in range(args.steps):
+        ts = time.perf_counter()
         step()
-        ms, n = rs.last_solve_timing()        # waits for this step's solver events
-        kern_ms += ms
-        kern_launches += n
+        launch = rs.last_solve_launch_ms()      # waits for this step's solver events
+        torch.cuda.synchronize()
+        step_ms.append(1000.0 * (time.perf_counter() - ts))
+        pair_ms.append(launch[0])
+        scan_ms.append(sum(launch[1:]))
+        kern_ms += sum(launch)
+        kern_launches += len(launch)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_per_step = 1000.0 * wall / args.steps
     iters = out["iters"].cpu().numpy()
     status = out["status"].cpu().numpy()
-    alg_bytes = algorithmic_bytes(iters, M, H, W, p.levels, p.max_iter) * args.steps
+    alg_step = algorithmic_bytes(iters, M, H, W, p.levels, p.max_iter)
+    alg_bytes = alg_step * args.steps
     achieved = alg_bytes / (kern_ms / 1000.0) / 1e9
     value = M / (ms_per_step / 1000.0)
+    mean = lambda xs: sum(xs) / len(xs)
 
     result = {
         "metric": METRIC, "value": round(value, 3), "unit": "frames/s", "n_gpus": 1,
@@ -172,24 +213,44 @@ def main():
                    "plan_ops": int(len(ops)), "plan_levels": int(n_levels),
                    "registrations": int(n_regs), "max_iter": p.max_iter, "rel_tol": p.rel_tol,
                    "tau": p.tau, "lambda": p.lam, "storage": "f32", "parallelism": "single-gpu",
+                   "execution": "batched: one persistent launch per scan level, replayed from a hipGraph",
+                   "tile_rows": TILE_ROWS, "max_group": MAX_GROUP,
                    "mean_iterations_per_level": [round(float(x), 2) for x in iters.mean(axis=0)],
                    "maxiter_registrations": int((status & 1).sum()),
                    "aborted_registrations": int((status & 4).sum())},
+        "step_ms": [round(x, 3) for x in step_ms],
+        "step_ms_ci95": None if ci95(step_ms) is None else round(ci95(step_ms), 3),
+        "phases_ms": {"pairwise": round(mean(pair_ms), 3), "scan_levels": round(mean(scan_ms), 3),
+                      "scan_only_frames_per_s": round(M / (mean(scan_ms) / 1000.0), 3)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
                      "kernel": "k_persistent (batched gradient-descent solver)",
                      "kernel_ms_per_step": round(kern_ms / args.steps, 3),
                      "launches_per_step": kern_launches // max(1, args.steps),
-                     "algorithmic_bytes_per_step": alg_bytes // args.steps},
+                     "kernel_ms_per_launch": round(kern_ms / max(1, kern_launches), 4),
+                     "algorithmic_bytes_per_step": alg_step},
         "cpu_baseline": base,
     }
 
+    if not args.no_dataflow:
+        step("dataflow", False)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(args.steps):
+            t1 = time.perf_counter()
+            step("dataflow", False)
+            torch.cuda.synchronize()
+            ts.append(1000.0 * (time.perf_counter() - t1))
+        result["dataflow"] = {"value": round(M / (mean(ts) / 1000.0), 3), "unit": "frames/s",
+                              "ms_per_step": round(mean(ts), 3), "steps": args.steps,
+                              "mode": "whole scan in one persistent launch, device ready queue"}
+
     if not args.no_plain:
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        rs.scan_run(frames, p, cfg.algo, cfg.chunk, cfg.global_algo, mode="plain", out=out)
+        t1 = time.perf_counter()
+        step("plain", False)
         torch.cuda.synchronize()
-        plain_s = time.perf_counter() - t0
+        plain_s = time.perf_counter() - t1
         result["plain"] = {"value": round(M / plain_s, 3), "unit": "frames/s", "steps": 1,
                            "ms_per_step": round(1000 * plain_s, 1),
                            "mode": "one registration at a time, one launch per iteration, host energy read-back"}

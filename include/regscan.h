@@ -258,15 +258,21 @@ int scan_run(const float* frames, int N, int H, int W, const reg_params_t* p,
  * number of launches.  HOST outputs; waits for those events. */
 int reg_last_solve_timing(double* total_ms, int* launches);
 
+/* The same probe per launch, in launch order (for scan_run in REG_BATCHED
+ * mode: the pairwise phase, then one launch per scan level): up to `cap`
+ * durations in milliseconds into ms[] (HOST), the number of launches into
+ * *n.  A replayed graph (SCAN_F_GRAPH) records these events itself. */
+int reg_last_solve_launch_ms(double* ms, int cap, int* n);
+
 /* Library tuning.
  *   tile_rows  tile height of the finest pyramid level (multiple of 4, 4..64;
  *              level l uses max(4, tile_rows / 4^l)); it fixes the order in
  *              which energies are summed, so results depend on it (within
- *              rounding), not on the other two settings.  Default 32.
+ *              rounding), not on the other two settings.  Default 64.
  *   max_group  cap on workgroups per registration in REG_BATCHED and
- *              REG_DATAFLOW modes (1..128).  Default 32.
+ *              REG_DATAFLOW modes (1..128).  Default 64.
  *   resident   1: pyramid levels whose tiles are 64 columns wide, whose tile
- *              height is a power of two <= 32 dividing the level height, and
+ *              height is a power of two <= 64 dividing the level height, and
  *              whose tile count fits the group keep the field in registers
  *              across iterations (one workgroup per tile); 0: every level
  *              streams the field through memory.  Default 1.

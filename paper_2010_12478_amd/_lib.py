@@ -26,7 +26,8 @@ EXPORTS = (
     "reg_warp_adjoint", "reg_warp_adjoint_f64", "reg_energy_grad", "reg_energy_grad_f64",
     "reg_pyramid_energy", "reg_pyramid_energy_f64", "reg_pyramid_energy_backward",
     "reg_pyramid_energy_backward_f64", "reg_compose", "reg_restrict", "reg_prolong",
-    "reg_solve_batch", "scan_plan", "scan_run", "reg_last_solve_timing", "reg_set_tuning",
+    "reg_solve_batch", "scan_plan", "scan_run", "reg_last_solve_timing", "reg_last_solve_launch_ms",
+    "reg_set_tuning",
     "reg_autotune", "reg_release",
 )
 
@@ -76,6 +77,7 @@ _SIGS = {
                       _P, _P, _P, _P, _P]),
     "reg_last_solve_timing": (_I, [ctypes.POINTER(_D), ctypes.POINTER(_I)]),
     "reg_set_tuning": (_I, [_I, _I, _I]),
+    "reg_last_solve_launch_ms": (_I, [ctypes.POINTER(ctypes.c_double), _I, ctypes.POINTER(_I)]),
     "reg_autotune": (_I, [_I, _I, _I, _I, ctypes.POINTER(_I), ctypes.POINTER(_I), _P]),
     "reg_release": (None, []),
 }

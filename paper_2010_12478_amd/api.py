@@ -221,6 +221,15 @@ def last_solve_timing():
     return ms.value, n.value
 
 
+def last_solve_launch_ms():
+    """Per-launch device durations (ms) of the last solve / scan_run."""
+    n = ctypes.c_int(0)
+    check(lib.reg_last_solve_launch_ms(None, 0, ctypes.byref(n)))
+    buf = (ctypes.c_double * max(n.value, 1))()
+    check(lib.reg_last_solve_launch_ms(buf, n.value, ctypes.byref(n)))
+    return list(buf)[:n.value]
+
+
 def set_tuning(tile_rows=0, max_group=0, resident=None):
     """Tile height of the finest level, workgroup cap per registration, and
     whether levels that fit run register-resident (None keeps it)."""

@@ -58,8 +58,8 @@ struct State {
   int device = -1;
   int n_cu = 0;
   int blocks_per_cu = 0;
-  int tile_rows = 32;
-  int max_group = 32;
+  int tile_rows = 64;
+  int max_group = 64;
   bool resident = true;
   unsigned spin_limit = 1u << 22;   // ~seconds of polling before the watchdog aborts a run
   DevBuf pyr, slots, part, ctrl, tasks, nodes, upair, iters, status, misc, lvl, flow;
@@ -70,6 +70,7 @@ struct State {
     std::string key;
     unsigned generation;
     hipGraphExec_t exec;
+    size_t n_events;      // timing event pairs recorded by a replay (pool entries 0..n-1)
     DevBuf tasks, flow;   // descriptors owned by the graph
   };
   std::vector<Graph> graphs;
@@ -184,6 +185,9 @@ SolveArgs base_args(const float* const lv[kMaxLevels], int H, int W, const reg_p
   }
   a.resident = g.resident ? 1 : 0;
   a.slot_floats = slot_floats_for(H, W, p->levels, a.lvl_off, &a.bufB_off);
+  a.colx_off = a.slot_floats;
+  a.colx_stride = (size_t)16 * kMaxRPT * a.max_tiles;
+  a.slot_floats += 2 * a.colx_stride;
   a.spin_limit = g.spin_limit;
   return a;
 }
@@ -195,7 +199,7 @@ struct Launch {
 };
 
 // Workgroups per registration.  When the finest level can run
-// register-resident (64-column tiles, tile height a power of two <= 32 that
+// register-resident (64-column tiles, tile height a power of two <= 64 that
 // divides the height) and its tile count fits max_group, the group gets one
 // workgroup per tile.  Otherwise the largest power of two within max_group
 // and the tile count; batched runs stop doubling once fewer groups than tasks
@@ -204,7 +208,7 @@ int group_size(int n_tasks, int H, int W, bool dataflow) {
   const int slots = g.blocks_per_cu * g.n_cu;
   const int th = g.tile_rows;
   const int tiles = tiles_of(H, W, th);
-  if (g.resident && W % kTileW == 0 && H % th == 0 && th <= 32 && (th & (th - 1)) == 0 &&
+  if (g.resident && W % kTileW == 0 && H % th == 0 && th <= 4 * kMaxRPT && (th & (th - 1)) == 0 &&
       tiles <= g.max_group && tiles <= kMaxGroup && 8 * tiles <= slots)
     return tiles;
   int gs = 1;
@@ -812,11 +816,9 @@ int scan_run(const float* frames, int N, int H, int W, const reg_params_t* p, in
     }
     for (auto& gr : g.graphs) {
       if (gr.key == key && gr.generation == g.generation) {
-        g.events_used = 0;
-        hipEvent_t* ev = next_events();
-        if (ev) HIPCHK(hipEventRecord(ev[0], s));
+        // the graph records the timing events of its solver launches itself
         HIPCHK(hipGraphLaunch(gr.exec, s));
-        if (ev) HIPCHK(hipEventRecord(ev[1], s));
+        g.events_used = gr.n_events;
         return REG_OK;
       }
     }
@@ -905,7 +907,9 @@ int scan_run(const float* frames, int N, int H, int W, const reg_params_t* p, in
   hipStream_t cs;
   HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
   HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-  const int rc = enqueue(cs, (const TaskDesc*)gr.tasks.p, (int*)gr.flow.p, false);
+  g.events_used = 0;
+  const int rc = enqueue(cs, (const TaskDesc*)gr.tasks.p, (int*)gr.flow.p, true);
+  gr.n_events = g.events_used;
   hipGraph_t graph = nullptr;
   const hipError_t ec = hipStreamEndCapture(cs, &graph);
   (void)hipStreamDestroy(cs);
@@ -917,6 +921,19 @@ int scan_run(const float* frames, int N, int H, int W, const reg_params_t* p, in
   if (ei != hipSuccess) return fail(REG_E_HIP, "graph instantiation failed: %s", hipGetErrorString(ei));
   gr.generation = gen;
   g.graphs.push_back(gr);
+  return REG_OK;
+}
+
+int reg_last_solve_launch_ms(double* ms, int cap, int* n) {
+  std::lock_guard<std::recursive_mutex> lk(g_mu);
+  if (cap < 0 || (cap > 0 && !ms)) return fail(REG_E_INVALID, "launch_ms: cap %d with output %p", cap, (void*)ms);
+  for (size_t q = 0; q < g.events_used && (int)q < cap; ++q) {
+    HIPCHK(hipEventSynchronize(g.events[q].second));
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, g.events[q].first, g.events[q].second));
+    ms[q] = t;
+  }
+  if (n) *n = (int)g.events_used;
   return REG_OK;
 }
 

@@ -43,6 +43,8 @@ struct SolveArgs {
   size_t slot_floats;
   size_t lvl_off[kMaxLevelsHost];     // offsets of the pyramid-shaped buffer A per level
   size_t bufB_off;       // offset of buffer B inside a slot
+  size_t colx_off;       // column-halo exchange area inside a slot: 2 parities of colx_stride floats
+  size_t colx_stride;    // floats per parity: 16 * kMaxRPT per tile
   unsigned spin_limit;
   // dataflow execution (dataflow != 0): task t enters ready[] (tail ctrl[3],
   // head ctrl[2]) once deps[t] drops to 0; the consumers of task t are

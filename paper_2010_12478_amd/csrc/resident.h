@@ -9,17 +9,20 @@
 //   - rows: every wavefront stores its first and last row, and loads the row
 //     above its first and below its last (rows clamped to the grid: at the
 //     border the neighbour is the pixel itself, so the difference is 0);
-//   - columns: lanes 0 and 63 store their column, and one wave-wide load
-//     fetches the columns left and right of the tile for the wavefront's
-//     rows; a cross-lane permute puts each row's pair into lanes 0 / 63.
+//   - columns: lanes 0 and 63 store their column into a small exchange
+//     buffer (contiguous per tile, side and wavefront), and one wave-wide
+//     load fetches the columns left and right of the tile for the
+//     wavefront's rows; a cross-lane permute puts each row's pair into lanes
+//     0 / 63.
 // The field is updated in place, row by row (the old value of the row above
 // is kept aside for the next row).  The state an iteration starts from is
 // copied to LDS first: when the energy of that iteration stops the level, it
 // is the result.  The halo values of iteration t are read from U[t % 2] and
 // those of its result written to U[(t + 1) % 2] (full-size fields of which
-// only halo positions are written), so a reader in iteration t reads what its
-// neighbours wrote before the barrier that ended iteration t - 1, and the
-// writers of iteration t write the other buffer.
+// only halo rows are written; the columns likewise alternate between two
+// exchange buffers), so a reader in iteration t reads what its neighbours
+// wrote before the barrier that ended iteration t - 1, and the writers of
+// iteration t write the other buffer.
 //
 // Per pixel and iteration the arithmetic is pixel_eval and gd_update, the tile
 // energy is summed in the order of the streaming sweep with the same tile
@@ -50,14 +53,37 @@ __device__ __forceinline__ float lane_pull(float v, int src_lane) {
   return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(src_lane << 2, __builtin_bit_cast(int, v)));
 }
 
-constexpr int kMaxRPT = 8;   // rows per thread at most (tile height 32)
-
 struct ResidentTile {
   int h, w, hw;
   int xt, y0;        // the tile's first column, the wavefront's first row
+  int tile, tx, ntx, wave;
   int lane;
   double tau, lam;
 };
+
+// Column-halo exchange buffer (one parity): for every tile, side (0: its
+// first column, 1: its last), wavefront and component the wavefront's RPT
+// rows, contiguous, so a wavefront reads each neighbouring column it needs
+// from one 2 RPT-float run.
+template <int RPT>
+__device__ __forceinline__ int colx_index(int tile, int side, int wave, int comp, int r) {
+  return (((tile * 2 + side) * 4 + wave) * 2 + comp) * RPT + r;
+}
+
+// Lanes 0 and 63 store the tile's first and last columns of (sx, sy).
+template <int RPT>
+__device__ __forceinline__ void store_columns(const ResidentTile& P, const float (&sx)[RPT], const float (&sy)[RPT],
+                                              const ReadBuf& cx, int lane) {
+  if (lane == 0 || lane == kWave - 1) {
+    const int side = lane == 0 ? 0 : 1;
+    const int b = colx_index<RPT>(P.tile, side, P.wave, 0, 0);
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      cx.st32(b + r, 0, sx[r]);
+      cx.st32(b + RPT + r, 0, sy[r]);
+    }
+  }
+}
 
 // One iteration on the state (sx, sy), updated in place (R and T read
 // through rb and tb): returns this lane's energy sum over its rows (in row
@@ -66,8 +92,9 @@ struct ResidentTile {
 // (RPT float2 per thread, LDS).
 template <int RPT>
 __device__ __forceinline__ double resident_step(const ResidentTile& P, float (&sx)[RPT], float (&sy)[RPT],
-                                                const SharedBuf& ucur, const ReadBuf& unext, const ReadBuf& tb,
-                                                const ReadBuf& rb, float2* roll) {
+                                                const SharedBuf& ucur, const ReadBuf& unext, const SharedBuf& ccur,
+                                                const ReadBuf& cnext, const ReadBuf& tb, const ReadBuf& rb,
+                                                float2* roll) {
   // P.h, P.w, P.xt, P.y0 are wave-uniform: row offsets go to the scalar
   // offset of the buffer instructions, the per-lane offset is the lane
   const int h = P.h, w = P.w, hw = P.hw, y0 = P.y0, xt = P.xt;
@@ -80,11 +107,16 @@ __device__ __forceinline__ double resident_step(const ResidentTile& P, float (&s
   const int ru = __mul24(max(y0 - 1, 0), w) + xt, rd = __mul24(min(y0 + RPT, h - 1), w) + xt;
   const float hux = ucur.f32(lane, ru), huy = ucur.f32(lane, hw + ru);
   const float hdx = ucur.f32(lane, rd), hdy = ucur.f32(lane, hw + rd);
-  // lane k < 4 RPT: side k / (2 RPT) (0 left, 1 right), component (k / RPT) & 1, row k % RPT
+  // lane k < 4 RPT: halo side k / (2 RPT) (0 left, 1 right), component
+  // (k / RPT) & 1, row k % RPT; the left halo is the last column of the tile
+  // to the left (at the grid's edge: this tile's own first column), the
+  // right halo the first column of the tile to the right
   const int k = lane & (4 * RPT - 1);
   const int side = k / (2 * RPT), comp = (k / RPT) & 1, rk = k & (RPT - 1);
-  const int col = side ? min(xt + kTileW, w - 1) : max(xt - 1, 0);
-  const float hcol = ucur.f32(comp * hw + __mul24(rk, w) + col, __mul24(y0, w));
+  int src = P.tile, src_side = side;
+  if (side == 0 && P.tx > 0) src = P.tile - 1, src_side = 1;
+  if (side == 1 && P.tx < P.ntx - 1) src = P.tile + 1, src_side = 0;
+  const float hcol = ccur.f32(colx_index<RPT>(src, src_side, P.wave, comp, rk));
   const int sel = lane == kWave - 1 ? 2 * RPT : 0;   // lane 63 pulls the right column, the others the left
 
   // the state this iteration starts from
@@ -150,14 +182,7 @@ __device__ __forceinline__ double resident_step(const ResidentTile& P, float (&s
       unext.st32(lane, q, sx[RPT - 1]);
       unext.st32(lane, hw + q, sy[RPT - 1]);
     }
-    if (RPT > 2 && (lane == 0 || lane == kWave - 1)) {
-#pragma unroll
-      for (int r = 1; r < RPT - 1; ++r) {
-        const int q = __mul24(y0 + r, w) + xt;
-        unext.st32(lane, q, sx[r]);
-        unext.st32(lane, hw + q, sy[r]);
-      }
-    }
+    store_columns<RPT>(P, sx, sy, cnext, lane);
   }
   return acc;
 }

@@ -178,7 +178,7 @@ __device__ bool energy_barrier(const Group& G, unsigned long long* cur, double a
 // otherwise `iters` is the number of updates kept and `nonfinite` tells
 // whether an energy was not finite (then U0 is left as it is).
 template <int RPT>
-__device__ bool level_resident(const SolveArgs& a, const LevelView<float>& V, float* U0, float* U1, Group& G,
+__device__ bool level_resident(const SolveArgs& a, const LevelView<float>& V, float* U0, float* U1, float* slot, Group& G,
                                double* part, int& par, double* red, double* s_E, int* s_flag, float2* roll,
                                int& iters, bool& nonfinite) {
   int* abort_flag = a.ctrl + 1;
@@ -194,11 +194,17 @@ __device__ bool level_resident(const SolveArgs& a, const LevelView<float>& V, fl
   P.hw = h * w;
   P.lane = threadIdx.x & (kWave - 1);
   P.xt = (tile % ntx) * kTileW;
-  P.y0 = (tile / ntx) * th + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * RPT;
+  P.wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  P.y0 = (tile / ntx) * th + P.wave * RPT;
+  P.tile = tile;
+  P.tx = tile % ntx;
+  P.ntx = ntx;
   P.tau = V.tau;
   P.lam = V.lam;
   const ReadBuf tb(V.T), rb(V.R);
   float sx[RPT], sy[RPT];
+  float* colx0 = slot + a.colx_off;
+  float* colx1 = colx0 + a.colx_stride;
   {
     const SharedBuf u0(U0);
 #pragma unroll
@@ -207,6 +213,9 @@ __device__ bool level_resident(const SolveArgs& a, const LevelView<float>& V, fl
       sx[r] = active ? u0.f32(o) : 0.f;
       sy[r] = active ? u0.f32(P.hw + o) : 0.f;
     }
+    // the initial field's tile columns for the first iteration (made
+    // visible by the barrier below)
+    if (active) store_columns<RPT>(P, sx, sy, ReadBuf(colx0), P.lane);
   }
   roll += threadIdx.x;
   // energy slots: three buffers of a.max_tiles (>= g) words, this member's
@@ -216,21 +225,21 @@ __device__ bool level_resident(const SolveArgs& a, const LevelView<float>& V, fl
   if (threadIdx.x < 3) slots[threadIdx.x * sbuf + G.member] = kSlotEmpty;
   if (!group_sync(G, abort_flag, a.spin_limit, s_flag)) return false;
   double e_prev = 0.0;
-  int it = 0, slot = 0;
+  int it = 0, eslot = 0;
   bool rollback = false;
   nonfinite = false;
   for (; it < a.max_iter; ++it) {
-    const int nslot = slot == 2 ? 0 : slot + 1;
+    const int nslot = eslot == 2 ? 0 : eslot + 1;
     if (threadIdx.x == 0)
       __hip_atomic_store(slots + nslot * sbuf + G.member, kSlotEmpty, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const bool odd = it & 1;
-    const SharedBuf ucur(odd ? U1 : U0);
-    const ReadBuf unext(odd ? U0 : U1);
-    const double acc = active ? resident_step<RPT>(P, sx, sy, ucur, unext, tb, rb, roll) : 0.0;
+    const SharedBuf ucur(odd ? U1 : U0), ccur(odd ? colx1 : colx0);
+    const ReadBuf unext(odd ? U0 : U1), cnext(odd ? colx0 : colx1);
+    const double acc = active ? resident_step<RPT>(P, sx, sy, ucur, unext, ccur, cnext, tb, rb, roll) : 0.0;
     double E;
-    if (!energy_barrier(G, slots + slot * sbuf, acc, active, nt, abort_flag, a.spin_limit, red, s_E, s_flag, E))
+    if (!energy_barrier(G, slots + eslot * sbuf, acc, active, nt, abort_flag, a.spin_limit, red, s_E, s_flag, E))
       return false;
-    slot = nslot;
+    eslot = nslot;
     if (!isfinite(E)) {
       nonfinite = true;
       break;
@@ -315,13 +324,14 @@ __device__ bool run_task(const SolveArgs& a, const TaskDesc& d, Group& G, float*
     V.lam = a.lam;
     const int th = a.thl[l];
     const int nt = tiles_of(h, w, th);
-    if (a.resident && w % kTileW == 0 && h % th == 0 && nt <= G.g && th <= 32 && (th & (th - 1)) == 0) {
+    if (a.resident && w % kTileW == 0 && h % th == 0 && nt <= G.g && th <= 4 * kMaxRPT && (th & (th - 1)) == 0) {
       int it = 0;
       bool nf = false, ok = true;
-      if (th == 4) ok = level_resident<1>(a, V, cur, bufB, G, part, par, red, s_E, s_flag, roll, it, nf);
-      else if (th == 8) ok = level_resident<2>(a, V, cur, bufB, G, part, par, red, s_E, s_flag, roll, it, nf);
-      else if (th == 16) ok = level_resident<4>(a, V, cur, bufB, G, part, par, red, s_E, s_flag, roll, it, nf);
-      else ok = level_resident<8>(a, V, cur, bufB, G, part, par, red, s_E, s_flag, roll, it, nf);
+      if (th == 4) ok = level_resident<1>(a, V, cur, bufB, slot, G, part, par, red, s_E, s_flag, roll, it, nf);
+      else if (th == 8) ok = level_resident<2>(a, V, cur, bufB, slot, G, part, par, red, s_E, s_flag, roll, it, nf);
+      else if (th == 16) ok = level_resident<4>(a, V, cur, bufB, slot, G, part, par, red, s_E, s_flag, roll, it, nf);
+      else if (th == 32) ok = level_resident<8>(a, V, cur, bufB, slot, G, part, par, red, s_E, s_flag, roll, it, nf);
+      else ok = level_resident<16>(a, V, cur, bufB, slot, G, part, par, red, s_E, s_flag, roll, it, nf);
       if (!ok) return false;
       iters[l] = it;
       if (nf) {

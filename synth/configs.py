@@ -76,7 +76,7 @@ CONFIGS: dict[int, Config] = {
               SeriesSpec(256, 256, 256, spacing=8.0, drift=4.0, distort=0.5,
                          noise=0.1, seed=BASE_SEED + 2),
               SolverParams(levels=2, max_iter=200),
-              algo="hier", chunk=16, global_algo="lf"),
+              algo="hier", chunk=4, global_algo="lf"),
     3: Config(3, "series1024-512x512-hier",
               SeriesSpec(1024, 512, 512, spacing=8.0, drift=8.0, distort=1.5,
                          noise=0.1, extra_noise_frac=0.1, extra_noise=0.3,

@@ -147,7 +147,7 @@ def _reg(args):
 
 
 def test_full_size_series256_sampled_prefixes(rs):
-    """256 frames of 256x256, 2 levels, hierarchical plan (chunks of 16,
+    """256 frames of 256x256, 2 levels, hierarchical plan (chunks of 4,
     Ladner-Fischer global phase) in the benchmark's launch configuration.
     The oracle recomputes, in the plan's combination order, the prefixes
     phi_{0,1..6} of the first chunk, and the independent pairwise
@@ -159,7 +159,7 @@ def test_full_size_series256_sampled_prefixes(rs):
     S = make_series(cfg.series)
     frames = S.frames
     p = cfg.solver
-    rs.set_tuning(32, 32, resident=True)   # the library defaults, which the benchmark runs with
+    rs.set_tuning(64, 64, resident=True)   # the library defaults, which the benchmark runs with
     try:
         phi0, u_pair, iters, status = (host(t) for t in rs.scan_run(frames.cuda(), p, cfg.algo, cfg.chunk,
                                                                      cfg.global_algo, mode="batched"))

@@ -111,7 +111,7 @@ def test_tile_rows_match_oracle(rs, tile_rows):
         assert np.abs(host(u)[b] - w.u).max() <= TOL_PX
 
 
-@pytest.mark.parametrize("tile_rows", [4, 8, 16, 32])
+@pytest.mark.parametrize("tile_rows", [4, 8, 16, 32, 64])
 @pytest.mark.parametrize("H,W,levels", [(64, 64, 1), (128, 192, 2), (256, 128, 3)])
 def test_resident_levels_match_streaming_bitwise(rs, tile_rows, H, W, levels):
     """Register-resident levels (one workgroup per tile) give the same bits
