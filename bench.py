@@ -86,6 +86,36 @@ def algorithmic_bytes(iters, n_pair, H, W, levels, max_iter):
     return total
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_persistent_series256-256x256-hier.traffic.json")
+
+
+def kernel_sources_sha256():
+    """Hash of the HIP library sources the solver kernel is built from."""
+    import hashlib
+    d = os.path.join(ROOT, "paper_2010_12478_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        h.update(f.encode())
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per solver launch from the committed rocprofv3 counter runs
+    (FETCH_SIZE and WRITE_SIZE, each scaled by what it reads for a plain
+    device copy of known size), or None once the sources have changed since
+    the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except OSError:
+        return None
+    if t.get("sources_sha256") != kernel_sources_sha256():
+        return None
+    return int(t["hbm_bytes_per_dispatch"])
+
+
 def ci95(xs):
     """Half-width of the 95% confidence interval of the mean (Student t)."""
     n = len(xs)
@@ -106,7 +136,7 @@ def cpu_baseline(cfg, frames_cpu, n_total_regs, sample):
     from concurrent.futures import ProcessPoolExecutor
 
     cores = min(len(os.sched_getaffinity(0)), 16)
-    sample = sample or 4 * cores
+    sample = min(sample or 16 * cores, frames_cpu.shape[0] - 1)
     fr = frames_cpu.double().numpy()
     p = cfg.solver
     args = [(fr[k - 1], fr[k], p) for k in range(1, sample + 1)]
@@ -223,12 +253,13 @@ def main():
         "phases_ms": {"pairwise": round(mean(pair_ms), 3), "scan_levels": round(mean(scan_ms), 3),
                       "scan_only_frames_per_s": round(M / (mean(scan_ms) / 1000.0), 3)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": None,
+                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(),
                      "kernel": "k_persistent (batched gradient-descent solver)",
                      "kernel_ms_per_step": round(kern_ms / args.steps, 3),
                      "launches_per_step": kern_launches // max(1, args.steps),
                      "kernel_ms_per_launch": round(kern_ms / max(1, kern_launches), 4),
-                     "algorithmic_bytes_per_step": alg_step},
+                     "algorithmic_bytes_per_step": alg_step,
+                     "algorithmic_bytes_per_launch": alg_step // max(1, kern_launches // max(1, args.steps))},
         "cpu_baseline": base,
     }
 

@@ -21,34 +21,36 @@ __host__ __device__ inline bool level_stops(double e_prev, double e, double rel_
   return (e_prev - e) <= rel_tol * e_prev;
 }
 
-// Integer cell and in-cell fraction of a displacement component.  The cell is
-// decided on the float32 value; the fraction u - floor(u) is exact.  All
-// arithmetic of the kernels is double; stored data are float (or double in
-// the float64 instantiations).
-__device__ __forceinline__ void cell_of(float u, int& c, double& f) {
-  float fl = floorf(u);
-  fl = fminf(fmaxf(fl, -1048576.f), 1048576.f);   // NaN -> -2^20: taps clamp, value stays NaN
-  c = (int)fl;
-  f = (double)(u - fl);
+// Cell of a displacement component: its float32 floor fl (exact), and the
+// integer cell used to index taps, clamped to +-2^20 (NaN -> -2^20: the taps
+// clamp to the image and the value stays NaN).  The in-cell fraction is
+// u - fl formed in double, which is exact for every float32 u with
+// |u| >= 2^-29; formed in float32 it is not (u + 1 rounds for most u in
+// (-1, 0)).  All arithmetic of the kernels is double; stored data are float
+// (or double in the float64 instantiations).
+__device__ __forceinline__ float floor_cell(float u, int& c) {
+  const float fl = floorf(u);
+  c = (int)fminf(fmaxf(fl, -1048576.f), 1048576.f);
+  return fl;
 }
-__device__ __forceinline__ void cell_of_f(float u, int& c, float& f) {
-  float fl = floorf(u);
-  fl = fminf(fmaxf(fl, -1048576.f), 1048576.f);
-  c = (int)fl;
-  f = u - fl;
+__device__ __forceinline__ void cell_of(float u, int& c, double& f) {
+  const float fl = floor_cell(u, c);
+  f = (double)u - (double)fl;
 }
 __device__ __forceinline__ void cell_of(double u, int& c, double& f) {
-  float fl = floorf((float)u);
-  fl = fminf(fmaxf(fl, -1048576.f), 1048576.f);
-  c = (int)fl;
+  const float fl = floor_cell((float)u, c);
   f = u - (double)fl;
 }
 
 // Bilinear sample of img [H][W] at (x0 + wx, y0 + wy) with edge-clamped taps,
-// and its derivatives with respect to the sample position.
+// and its derivatives with respect to the sample position:
+//   s = (1 - wy) ((1 - wx) i00 + wx i01) + wy ((1 - wx) i10 + wx i11),
+// each product and sum one rounded float64 operation in that order (no
+// contraction), here and in the value-only forms below.
 template <typename S>
 __device__ __forceinline__ void bilin(const S* __restrict__ img, int H, int W, int x0, int y0,
                                       double wx, double wy, double& s, double& dsx, double& dsy) {
+#pragma clang fp contract(off)
   const int xa = clampi(x0, 0, W - 1), xb = clampi(x0 + 1, 0, W - 1);
   const int ya = clampi(y0, 0, H - 1), yb = clampi(y0 + 1, 0, H - 1);
   const double i00 = img[ya * W + xa], i01 = img[ya * W + xb];
@@ -62,6 +64,7 @@ __device__ __forceinline__ void bilin(const S* __restrict__ img, int H, int W, i
 template <typename S>
 __device__ __forceinline__ double bilin_value(const S* __restrict__ img, int H, int W, int x0, int y0,
                                               double wx, double wy) {
+#pragma clang fp contract(off)
   const int xa = clampi(x0, 0, W - 1), xb = clampi(x0 + 1, 0, W - 1);
   const int ya = clampi(y0, 0, H - 1), yb = clampi(y0 + 1, 0, H - 1);
   const double ox = 1.0 - wx, oy = 1.0 - wy;
@@ -120,6 +123,7 @@ using ReadBuf = BufView<0>;           // data no one writes during the launch
 // Bilinear value of a shared field (see SharedBuf) with clamped taps.
 __device__ __forceinline__ double bilin_value_shared(const SharedBuf& img, int H, int W, int x0, int y0,
                                                      double wx, double wy) {
+#pragma clang fp contract(off)
   const int xa = clampi(x0, 0, W - 1), xb = clampi(x0 + 1, 0, W - 1);
   const int ya = clampi(y0, 0, H - 1), yb = clampi(y0 + 1, 0, H - 1);
   const double ox = 1.0 - wx, oy = 1.0 - wy;

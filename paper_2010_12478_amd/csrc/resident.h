@@ -128,12 +128,12 @@ __device__ __forceinline__ double resident_step(const ResidentTile& P, float (&s
   // work in its own block, which bounds the registers in flight).
   constexpr int kAhead = RPT < 2 ? RPT : 2;
   float taps[RPT][4];
-  float fxs[RPT], fys[RPT], rr[RPT];
+  float flx[RPT], fly[RPT], rr[RPT];   // float32 floors of the state (the cells)
   auto gather = [&](int r) {
     rr[r] = rb.f32(lane, __mul24(y0 + r, w) + xt);
     int ix, iy;
-    cell_of_f(sx[r], ix, fxs[r]);
-    cell_of_f(sy[r], iy, fys[r]);
+    flx[r] = floor_cell(sx[r], ix);
+    fly[r] = floor_cell(sy[r], iy);
     const int xa = clampi(x + ix, 0, w - 1), xb = clampi(x + ix + 1, 0, w - 1);
     const int ya = __mul24(clampi(y0 + r + iy, 0, h - 1), w), yb = __mul24(clampi(y0 + r + iy + 1, 0, h - 1), w);
     taps[r][0] = tb.f32(ya + xa);
@@ -157,7 +157,8 @@ __device__ __forceinline__ double resident_step(const ResidentTile& P, float (&s
     const float cxs = sx[r], cys = sy[r];
     const double cx = cxs, cy = cys;
     double e, gx, gy;
-    pixel_eval(fxs[r], fys[r], taps[r][0], taps[r][1], taps[r][2], taps[r][3], rr[r], cx, cy, lx, ly, rx, ry,
+    pixel_eval(cx - (double)flx[r], cy - (double)fly[r], taps[r][0], taps[r][1], taps[r][2], taps[r][3], rr[r],
+               cx, cy, lx, ly, rx, ry,
                upx, upy, dx, dy, P.lam, e, gx, gy);
     acc += e;
     sx[r] = gd_update<float>(cx, gx, P.tau);

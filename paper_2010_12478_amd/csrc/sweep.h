@@ -55,34 +55,44 @@ __host__ __device__ inline int level_tile_rows(int th0, int l) {
 // in-cell fractions (fx, fy), with its position derivatives; residual
 // r = S - R; the neighbour values (c = pixel, l/r/u/d = left/right/up/down,
 // the pixel itself where the neighbour lies outside the grid).
-//   e  = r^2 + lam * ((rx - cx)^2 + (dx - cx)^2 + (ry - cy)^2 + (dy - cy)^2)
-//   g  = 2 r dS/dp + 2 lam * sum over the 4 neighbours of (c - n)
-// Every execution path evaluates a pixel through this function, so they agree
-// bitwise.
+//   S     = (1 - fy) ((1 - fx) i00 + fx i01) + fy ((1 - fx) i10 + fx i11)
+//   dS/dx = (1 - fy) (i01 - i00) + fy (i11 - i10)
+//   dS/dy = (1 - fx) (i10 - i00) + fx (i11 - i01)
+//   g     = (2 r) dS/dp + (2 lam) (((c - l) + (c - r)) + (c - u)) + (c - d))
+//   e     = r^2 + lam ((r - c)^2 + (d - c)^2) summed over both components
+// The gradient (and with it every stored iterate) is evaluated without
+// contraction: each product and sum is one rounded float64 operation, in the
+// order written above, so any implementation of these formulas in that
+// order produces the same bits.  The energy only feeds the stopping test and
+// may use fused operations.  Every execution path evaluates a pixel through
+// this function, so they agree bitwise.
 __device__ __forceinline__ void pixel_eval(double fx, double fy, double i00, double i01, double i10, double i11,
                                            double R, double cx, double cy, double lx, double ly, double rx,
                                            double ry, double ux, double uy, double dx, double dy, double lam,
                                            double& e, double& gx, double& gy) {
-  const double a = i01 - i00, b = i11 - i10, c = i10 - i00, d = i11 - i01;
-  const double top = fma(fx, a, i00), bot = fma(fx, b, i10);
-  const double s = fma(fy, bot - top, top);
-  const double sx = fma(fy, b - a, a);
-  const double sy = fma(fx, d - c, c);
+#pragma clang fp contract(off)
+  const double ox = 1.0 - fx, oy = 1.0 - fy;
+  const double s = oy * (ox * i00 + fx * i01) + fy * (ox * i10 + fx * i11);
+  const double sx = oy * (i01 - i00) + fy * (i11 - i10);
+  const double sy = ox * (i10 - i00) + fx * (i11 - i01);
   const double res = s - R;
-  const double hx = rx - cx, vx = dx - cx, hy = ry - cy, vy = dy - cy;
-  const double nbx = ((cx - lx) - hx) + ((cx - ux) - vx);
-  const double nby = ((cy - ly) - hy) + ((cy - uy) - vy);
-  const double reg = fma(hx, hx, vx * vx) + fma(hy, hy, vy * vy);
+  const double lxd = cx - lx, rxd = cx - rx, uxd = cx - ux, dxd = cx - dx;
+  const double lyd = cy - ly, ryd = cy - ry, uyd = cy - uy, dyd = cy - dy;
+  const double nbx = ((lxd + rxd) + uxd) + dxd;
+  const double nby = ((lyd + ryd) + uyd) + dyd;
+  const double r2 = 2.0 * res, l2 = 2.0 * lam;
+  gx = r2 * sx + l2 * nbx;
+  gy = r2 * sy + l2 * nby;
+  const double reg = fma(rxd, rxd, fma(dxd, dxd, fma(ryd, ryd, dyd * dyd)));
   e = fma(res, res, lam * reg);
-  const double r2 = res + res, l2 = lam + lam;
-  gx = fma(r2, sx, l2 * nbx);
-  gy = fma(r2, sy, l2 * nby);
 }
 
-// Gradient-descent update of one component, rounded once to the stored type.
+// Gradient-descent update of one component, c - tau g (one rounded product,
+// one rounded difference), rounded once to the stored type.
 template <typename S>
 __device__ __forceinline__ S gd_update(double c, double g, double tau) {
-  return (S)fma(-tau, g, c);
+#pragma clang fp contract(off)
+  return (S)(c - tau * g);
 }
 
 // Registers of one unit of work of a wavefront: rows [yb, ye) (at most kRB)
@@ -173,16 +183,13 @@ __device__ void sweep_tiles(const LevelView<S>& L, int first, int stride, int th
     const int xc = vx ? x : w - 1;
     // gathers of T for this unit
     S taps[kRB][4];
-    S fxs[kRB], fys[kRB];      // exact: the fraction of a stored value fits its type
+    float flx[kRB], fly[kRB];  // float32 floors of the displacement (the cells)
     if (A.yb < A.ye) {
 #pragma unroll
       for (int r = 0; r < kRB; ++r) {
         int ix, iy;
-        double fx, fy;
-        cell_of(A.ax[r + 1], ix, fx);
-        cell_of(A.ay[r + 1], iy, fy);
-        fxs[r] = (S)fx;
-        fys[r] = (S)fy;
+        flx[r] = floor_cell((float)A.ax[r + 1], ix);
+        fly[r] = floor_cell((float)A.ay[r + 1], iy);
         const int x0 = xc + ix, y0 = min(A.yb + r, h - 1) + iy;
         const int xa = clampi(x0, 0, w - 1), xb = clampi(x0 + 1, 0, w - 1);
         const int ya = __mul24(clampi(y0, 0, h - 1), w), yb = __mul24(clampi(y0 + 1, 0, h - 1), w);
@@ -218,7 +225,8 @@ __device__ void sweep_tiles(const LevelView<S>& L, int first, int stride, int th
         }
         const double cx = cxs, cy = cys;
         double e, gx, gy;
-        pixel_eval(fxs[r], fys[r], taps[r][0], taps[r][1], taps[r][2], taps[r][3], A.rr[r], cx, cy, lxs, lys,
+        pixel_eval(cx - (double)flx[r], cy - (double)fly[r], taps[r][0], taps[r][1], taps[r][2], taps[r][3],
+                   A.rr[r], cx, cy, lxs, lys,
                    rxs, rys, A.ax[r], A.ay[r], A.ax[r + 2], A.ay[r + 2], lam, e, gx, gy);
         if (vx) {
           accE += e;
@@ -248,42 +256,70 @@ __device__ void sweep_tiles(const LevelView<S>& L, int first, int stride, int th
   }
 }
 
+// Initial guess at fine pixel (x, y), in double.  kind 1: the composition
+// ua(x) + ub(x + ua(x)); kind 2: the field ua.
+template <typename S>
+__device__ __forceinline__ void init_fine(int kind, const S* __restrict__ ua, const S* __restrict__ ub, int H,
+                                          int W, int x, int y, double& vx, double& vy) {
+#pragma clang fp contract(off)
+  const size_t HW = (size_t)H * W;
+  const S ax = ua[y * W + x], ay = ua[HW + y * W + x];
+  if (kind == 1) {
+    int ix, iy;
+    double fx, fy;
+    cell_of(ax, ix, fx);
+    cell_of(ay, iy, fy);
+    vx = (double)ax + bilin_value(ub, H, W, x + ix, y + iy, fx, fy);
+    vy = (double)ay + bilin_value(ub + HW, H, W, x + ix, y + iy, fx, fy);
+  } else {
+    vx = (double)ax;
+    vy = (double)ay;
+  }
+}
+
+// The fine-level guess restricted D times by half the 2x2 block mean, at
+// pixel (X, Y) of the level D coarser, in double throughout.  Every level is
+// 0.5 * (0.25 * (((v00 + v01) + v10) + v11)) of the four values below it
+// (v00 at (2X, 2Y), v01 at (2X + 1, 2Y), v10 at (2X, 2Y + 1)), each one
+// rounded float64 operation, without contraction: the definition's order.
+template <int D, typename S>
+__device__ void init_restricted(int kind, const S* __restrict__ ua, const S* __restrict__ ub, int H, int W,
+                                int X, int Y, double& vx, double& vy) {
+#pragma clang fp contract(off)
+  if constexpr (D == 0) {
+    init_fine<S>(kind, ua, ub, H, W, X, Y, vx, vy);
+  } else {
+    double sx = 0.0, sy = 0.0;
+#pragma unroll 1
+    for (int q = 0; q < 4; ++q) {
+      double tx, ty;
+      init_restricted<D - 1, S>(kind, ua, ub, H, W, 2 * X + (q & 1), 2 * Y + (q >> 1), tx, ty);
+      sx = q == 0 ? tx : sx + tx;
+      sy = q == 0 ? ty : sy + ty;
+    }
+    vx = 0.5 * (0.25 * sx);
+    vy = 0.5 * (0.25 * sy);
+  }
+}
+
 // Initial guess of a registration on its coarsest level (pixel (X, Y)):
-// the fine-level guess restricted L-1 times by half the 2x2 block mean, i.e.
-// 2^-(L-1) times the mean over the 2^(L-1) x 2^(L-1) block.  kind 0: zero;
-// kind 1: the composition ua(x) + ub(x + ua(x)); kind 2: the field ua.
+// the fine-level guess restricted L-1 times by half the 2x2 block mean.
+// kind 0: zero; kind 1: the composition ua(x) + ub(x + ua(x)); kind 2: the
+// field ua.
 template <typename S>
 __device__ __forceinline__ void init_pixel(int kind, const S* __restrict__ ua, const S* __restrict__ ub,
                                            int H, int W, int levels, int X, int Y, double& vx, double& vy) {
-  if (kind == 0) {
-    vx = 0.0;
-    vy = 0.0;
-    return;
+  switch (kind == 0 ? -1 : levels - 1) {
+    case 0: init_restricted<0, S>(kind, ua, ub, H, W, X, Y, vx, vy); return;
+    case 1: init_restricted<1, S>(kind, ua, ub, H, W, X, Y, vx, vy); return;
+    case 2: init_restricted<2, S>(kind, ua, ub, H, W, X, Y, vx, vy); return;
+    case 3: init_restricted<3, S>(kind, ua, ub, H, W, X, Y, vx, vy); return;
+    case 4: init_restricted<4, S>(kind, ua, ub, H, W, X, Y, vx, vy); return;
+    case 5: init_restricted<5, S>(kind, ua, ub, H, W, X, Y, vx, vy); return;
+    case 6: init_restricted<6, S>(kind, ua, ub, H, W, X, Y, vx, vy); return;
+    case 7: init_restricted<7, S>(kind, ua, ub, H, W, X, Y, vx, vy); return;
+    default: vx = 0.0; vy = 0.0; return;
   }
-  const int F = 1 << (levels - 1);
-  const size_t HW = (size_t)H * W;
-  double sx = 0.0, sy = 0.0;
-  for (int dy = 0; dy < F; ++dy) {
-    const int y = Y * F + dy;
-    for (int dx = 0; dx < F; ++dx) {
-      const int x = X * F + dx;
-      const S ax = ua[y * W + x], ay = ua[HW + y * W + x];
-      if (kind == 1) {
-        int ix, iy;
-        double fx, fy;
-        cell_of(ax, ix, fx);
-        cell_of(ay, iy, fy);
-        sx += (double)ax + bilin_value(ub, H, W, x + ix, y + iy, fx, fy);
-        sy += (double)ay + bilin_value(ub + HW, H, W, x + ix, y + iy, fx, fy);
-      } else {
-        sx += (double)ax;
-        sy += (double)ay;
-      }
-    }
-  }
-  const double scale = 1.0 / ((double)F * F * F);
-  vx = sx * scale;
-  vy = sy * scale;
 }
 
 // Prolongation of a coarse displacement [2][hc][wc] to fine pixel (x, y):

@@ -6,7 +6,7 @@ part of the registration method's arithmetic: neither the oracle nor the HIP
 library imports anything from the other, both import from here.
 """
 from .configs import CONFIGS, SolverParams, SeriesSpec, get_config
-from .lattice import Series, make_series, ground_truth, lattice_image
+from .lattice import Series, clean_frame, make_series, ground_truth, lattice_image
 
 __all__ = ["CONFIGS", "SolverParams", "SeriesSpec", "get_config", "Series",
-           "make_series", "ground_truth", "lattice_image"]
+           "make_series", "ground_truth", "lattice_image", "clean_frame"]

@@ -126,3 +126,13 @@ def ground_truth(series: Series, i: int, k: int, iters: int = 60) -> np.ndarray:
         wkx, wky = _distortion(spec, series.theta[k], px, py)
         px, py = cx + wkx, cy + wky
     return torch.stack([px - xx, py - yy]).numpy()
+
+
+def clean_frame(series: Series, k: int) -> np.ndarray:
+    """Noise-free frame k of a generated series as float64 [H][W] (for masks)."""
+    spec = series.spec
+    yy, xx = torch.meshgrid(torch.arange(spec.height, dtype=torch.float64),
+                            torch.arange(spec.width, dtype=torch.float64), indexing="ij")
+    wx, wy = _distortion(spec, series.theta[k], xx, yy)
+    return lattice_image(spec, series.origin, xx - series.drift[k, 0] - wx,
+                         yy - series.drift[k, 1] - wy).numpy()
