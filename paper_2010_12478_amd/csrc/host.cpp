@@ -151,25 +151,46 @@ hipEvent_t* next_events() {
 
 // ------------------------------------------------------------------ pyramid
 
-// Levels 1..L-1 of all N frames into g.pyr; fills pyr pointers.
-int build_pyramid(const float* frames, int N, int H, int W, int L, const float* lv[kMaxLevels], hipStream_t s) {
+// The solver's padded pyramid of all N frames (levels 0..L-1, see SolveArgs)
+// in g.pyr.
+struct Pyr {
+  const float* lv[kMaxLevels];   // pixel (0, 0) of frame 0 of level l
+  int pitch[kMaxLevels];
+  size_t fstride[kMaxLevels];
+};
+
+int level_pitch(int w) { return (kPadLeft + w + 1 + 31) / 32 * 32; }
+
+int build_pyramid(const float* frames, int N, int H, int W, int L, Pyr& P, hipStream_t s) {
+  std::memset(&P, 0, sizeof P);
   size_t total = 0;
-  for (int l = 1; l < L; ++l) total += (size_t)N * (H >> l) * (W >> l);
+  for (int l = 0; l < L; ++l) {
+    P.pitch[l] = level_pitch(W >> l);
+    P.fstride[l] = (size_t)((H >> l) + 2) * P.pitch[l];
+    total += (size_t)N * P.fstride[l];
+  }
   TRY(ensure(g.pyr, total * sizeof(float)));
-  lv[0] = frames;
   float* p = (float*)g.pyr.p;
-  for (int l = 1; l < L; ++l) {
-    HIPCHK(launch_restrict(lv[l - 1], p, 1.0, N, H >> (l - 1), W >> (l - 1), false, s));
-    lv[l] = p;
-    p += (size_t)N * (H >> l) * (W >> l);
+  for (int l = 0; l < L; ++l) {
+    if (l == 0)
+      HIPCHK(launch_pad_level(frames, W, (size_t)H * W, true, p, P.pitch[0], N, H, W, s));
+    else
+      HIPCHK(launch_pad_level(P.lv[l - 1], P.pitch[l - 1], P.fstride[l - 1], false, p, P.pitch[l], N, H >> l,
+                              W >> l, s));
+    P.lv[l] = p + P.pitch[l] + kPadLeft;
+    p += (size_t)N * P.fstride[l];
   }
   return REG_OK;
 }
 
-SolveArgs base_args(const float* const lv[kMaxLevels], int H, int W, const reg_params_t* p) {
+SolveArgs base_args(const Pyr& P, int H, int W, const reg_params_t* p) {
   SolveArgs a;
   std::memset(&a, 0, sizeof a);
-  for (int l = 0; l < kMaxLevels; ++l) a.pyr[l] = l < p->levels ? lv[l] : nullptr;
+  for (int l = 0; l < kMaxLevels; ++l) {
+    a.pyr[l] = l < p->levels ? P.lv[l] : nullptr;
+    a.pitch[l] = P.pitch[l];
+    a.fstride[l] = P.fstride[l];
+  }
   a.H = H;
   a.W = W;
   a.levels = p->levels;
@@ -309,14 +330,14 @@ int run_plain(SolveArgs a, const std::vector<TaskDesc>& tasks, const TaskDesc* d
         cur = start(l);
       }
       float* other = bufB;
-      const float* R = a.pyr[l] + (size_t)d.ref * h * w;
-      const float* T = a.pyr[l] + (size_t)d.tmpl * h * w;
+      const float* R = a.pyr[l] + (size_t)d.ref * a.fstride[l];
+      const float* T = a.pyr[l] + (size_t)d.tmpl * a.fstride[l];
       const int th = a.thl[l];
       const int nt = tiles_of(h, w, th);
       double e_prev = 0.0;
       int it = 0;
       for (; it < a.max_iter; ++it) {
-        HIPCHK(launch_plain_sweep(R, T, cur, other, h, w, a.tau, a.lam, th, part, s));
+        HIPCHK(launch_plain_sweep(R, T, a.pitch[l], cur, other, h, w, a.tau, a.lam, th, part, s));
         HIPCHK(launch_plain_reduce(part, nt, dE, s));
         HIPCHK(hipMemcpyAsync(g.h_E, dE, sizeof(double), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
@@ -647,9 +668,9 @@ int reg_solve_batch(const float* frames, int N, int H, int W, const int32_t* ref
       return fail(REG_E_INVALID, "frame index out of range at item %d", b);
   TRY(ensure_device());
   hipStream_t s = (hipStream_t)stream;
-  const float* lv[kMaxLevels] = {};
-  TRY(build_pyramid(frames, N, H, W, p->levels, lv, s));
-  SolveArgs a = base_args(lv, H, W, p);
+  Pyr P;
+  TRY(build_pyramid(frames, N, H, W, p->levels, P, s));
+  SolveArgs a = base_args(P, H, W, p);
   const size_t nf = (size_t)2 * H * W;
   std::vector<TaskDesc> tasks(B);
   for (int b = 0; b < B; ++b) {
@@ -858,9 +879,9 @@ int scan_run(const float* frames, int N, int H, int W, const reg_params_t* p, in
 
   // every launch of the run; graph capture records exactly these
   auto enqueue = [&](hipStream_t st, const TaskDesc* d_tasks, int* dflow, bool timed) -> int {
-    const float* lv[kMaxLevels] = {};
-    TRY(build_pyramid(frames, N, H, W, L, lv, st));
-    SolveArgs a = base_args(lv, H, W, p);
+    Pyr P;
+    TRY(build_pyramid(frames, N, H, W, L, P, st));
+    SolveArgs a = base_args(P, H, W, p);
     if (mode == REG_DATAFLOW) {
       TRY(run_dataflow(a, d_tasks, (int)T, dflow + flow_used, dflow, dflow + flow_used + T, dflow + T, M,
                        dflow + 2 * T, dflow + 3 * T + 1, st, timed));

@@ -26,7 +26,11 @@ struct TaskDesc {
 };
 
 struct SolveArgs {
-  const float* pyr[kMaxLevelsHost];   // level l of frame f at pyr[l] + f*(H>>l)*(W>>l)
+  // padded pyramid: pixel (0, 0) of level l of frame f at pyr[l] + f * fstride[l],
+  // rows pitch[l] apart, a one-pixel replicate border around every frame
+  const float* pyr[kMaxLevelsHost];
+  size_t fstride[kMaxLevelsHost];
+  int pitch[kMaxLevelsHost];
   int H, W, levels;
   int max_iter, fixed_iter;
   double tau, lam;
@@ -60,6 +64,15 @@ size_t slot_floats_for(int H, int W, int levels, size_t* lvl_off, size_t* bufB_o
 
 // kernels.hip
 hipError_t launch_restrict(const void* in, void* out, double scale, int B, int H, int W, bool f64, hipStream_t s);
+// Padded pyramid level (see SolveArgs): dst holds N frames of (h + 2) rows of
+// `pitch` floats, pixel (0, 0) at dst + pitch + kPadLeft, every frame
+// fstride = (h + 2) * pitch floats apart; rows -1 .. h and columns -1 .. w
+// hold the nearest pixel's value.  src == level 0: frames [N][h][w]
+// (copied); otherwise the padded level below (sp = its pitch, sfs = its
+// frame stride, pointer at its pixel (0, 0)), restricted by 2x2 block means.
+constexpr int kPadLeft = 32;   // columns before pixel 0 (keeps rows 128-byte aligned)
+hipError_t launch_pad_level(const float* src, int sp, size_t sfs, bool copy, float* dst, int pitch, int N, int h,
+                            int w, hipStream_t s);
 hipError_t launch_prolong(const float* uc, float* uf, int B, int Hf, int Wf, hipStream_t s);
 hipError_t launch_compose(const float* uij, const float* ujk, float* out, int B, int H, int W, hipStream_t s);
 hipError_t launch_warp(const void* T, const void* u, void* out, int B, int H, int W, bool f64, hipStream_t s);
@@ -85,7 +98,7 @@ hipError_t launch_reset_dataflow(int* deps, const int* deps0, int* ready, const 
                                  int* ctrl, int n_ready0, hipStream_t s);
 hipError_t launch_plain_init(const TaskDesc* d_task, const SolveArgs& a, float* dst, hipStream_t s);
 hipError_t launch_plain_prolong(const float* uc, float* uf, int h, int w, hipStream_t s);
-hipError_t launch_plain_sweep(const float* R, const float* T, const float* u, float* un, int h, int w,
+hipError_t launch_plain_sweep(const float* R, const float* T, int pitch, const float* u, float* un, int h, int w,
                               double tau, double lam, int th, double* part, hipStream_t s);
 hipError_t launch_plain_reduce(const double* part, int n, double* E, hipStream_t s);
 hipError_t launch_copy(const float* src, float* dst, size_t n, hipStream_t s);   // src == nullptr: fill NaN

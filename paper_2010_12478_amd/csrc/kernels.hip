@@ -31,6 +31,33 @@ __global__ void __launch_bounds__(kEW) k_restrict(const S* __restrict__ in, S* _
   }
 }
 
+// Padded pyramid level: element (Y, X), Y in [-1, h], X in [-1, w], of frame
+// f holds pixel (clamp(Y), clamp(X)) of the level: a copy of the frame
+// (COPY) or the 2x2 block mean of the padded level below, in the order and
+// precision of k_restrict.
+template <bool COPY>
+__global__ void __launch_bounds__(kEW) k_pad_level(const float* __restrict__ src, int sp, size_t sfs,
+                                                   float* __restrict__ dst, int pitch, int N, int h, int w) {
+  const int hp = h + 2, wp = w + 2;
+  const size_t n = (size_t)N * hp * wp;
+  const size_t fstride = (size_t)hp * pitch;
+  for (size_t t = blockIdx.x * (size_t)kEW + threadIdx.x; t < n; t += (size_t)gridDim.x * kEW) {
+    const size_t f = t / ((size_t)hp * wp);
+    const int r = (int)(t - f * hp * wp);
+    const int Y = r / wp - 1, X = r - (Y + 1) * wp - 1;
+    const int yc = clampi(Y, 0, h - 1), xc = clampi(X, 0, w - 1);
+    float v;
+    if (COPY) {
+      v = src[f * h * w + (size_t)yc * w + xc];
+    } else {
+      const float* q = src + f * sfs + (size_t)(2 * yc) * sp + 2 * xc;
+      const double sum = (((double)q[0] + (double)q[1]) + (double)q[sp]) + (double)q[sp + 1];
+      v = (float)(0.25 * sum);
+    }
+    dst[f * fstride + (size_t)(Y + 1) * pitch + kPadLeft + X] = v;
+  }
+}
+
 __global__ void __launch_bounds__(kEW) k_prolong(const float* __restrict__ uc, float* __restrict__ uf,
                                                  int B, int Hf, int Wf) {
   const int hc = Hf >> 1, wc = Wf >> 1;
@@ -126,9 +153,10 @@ __global__ void __launch_bounds__(kWG) k_energy_tiles(const S* __restrict__ R, c
   L.out = grad ? grad + b * 2 * HW : nullptr;
   L.h = H;
   L.w = W;
+  L.pitch = W;
   L.tau = 0.0;
   L.lam = lam;
-  sweep_tiles<S, WRITE, GNORM>(L, blockIdx.x, gridDim.x, th, red, part + (size_t)b * nt,
+  sweep_tiles<S, WRITE, GNORM, false>(L, blockIdx.x, gridDim.x, th, red, part + (size_t)b * nt,
                                gpart + (size_t)b * nt);
 }
 
@@ -244,6 +272,17 @@ hipError_t launch_restrict(const void* in, void* out, double scale, int B, int H
   else
     hipLaunchKernelGGL(k_restrict<float>, dim3(ew_blocks(n)), dim3(kEW), 0, s, (const float*)in,
                        (float*)out, scale, B, H, W);
+  return hipGetLastError();
+}
+
+hipError_t launch_pad_level(const float* src, int sp, size_t sfs, bool copy, float* dst, int pitch, int N, int h,
+                            int w, hipStream_t s) {
+  const size_t n = (size_t)N * (h + 2) * (w + 2);
+  if (n == 0) return hipSuccess;
+  if (copy)
+    hipLaunchKernelGGL(k_pad_level<true>, dim3(ew_blocks(n)), dim3(kEW), 0, s, src, sp, sfs, dst, pitch, N, h, w);
+  else
+    hipLaunchKernelGGL(k_pad_level<false>, dim3(ew_blocks(n)), dim3(kEW), 0, s, src, sp, sfs, dst, pitch, N, h, w);
   return hipGetLastError();
 }
 

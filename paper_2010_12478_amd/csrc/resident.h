@@ -55,6 +55,7 @@ __device__ __forceinline__ float lane_pull(float v, int src_lane) {
 
 struct ResidentTile {
   int h, w, hw;
+  int pitch;         // row pitch of R and T (padded pyramid: one-pixel replicate border)
   int xt, y0;        // the tile's first column, the wavefront's first row
   int tile, tx, ntx, wave;
   int lane;
@@ -85,9 +86,9 @@ __device__ __forceinline__ void store_columns(const ResidentTile& P, const float
   }
 }
 
-// One iteration on the state (sx, sy), updated in place (R and T read
-// through rb and tb): returns this lane's energy sum over its rows (in row
-// order).  `ucur` holds the halo of the state; the halo-facing values of the
+// One iteration on the state (sx, sy), updated in place (R read through rb
+// from pixel (0, 0), T through tb from its border element (-1, -1)): returns
+// this lane's energy over its rows (accumulated in row order).  `ucur` holds the halo of the state; the halo-facing values of the
 // new state are stored through `unext`; the old state is saved to `roll`
 // (RPT float2 per thread, LDS).
 template <int RPT>
@@ -97,7 +98,7 @@ __device__ __forceinline__ double resident_step(const ResidentTile& P, float (&s
                                                 float2* roll) {
   // P.h, P.w, P.xt, P.y0 are wave-uniform: row offsets go to the scalar
   // offset of the buffer instructions, the per-lane offset is the lane
-  const int h = P.h, w = P.w, hw = P.hw, y0 = P.y0, xt = P.xt;
+  const int h = P.h, w = P.w, hw = P.hw, y0 = P.y0, xt = P.xt, pitch = P.pitch;
   // per-lane values derived afresh every iteration rather than held in
   // registers across the level (the empty asm hides their invariance)
   int lane = P.lane;
@@ -130,23 +131,26 @@ __device__ __forceinline__ double resident_step(const ResidentTile& P, float (&s
   float taps[RPT][4];
   float flx[RPT], fly[RPT], rr[RPT];   // float32 floors of the state (the cells)
   auto gather = [&](int r) {
-    rr[r] = rb.f32(lane, __mul24(y0 + r, w) + xt);
+    rr[r] = rb.f32(lane, __mul24(y0 + r, pitch) + xt);
     int ix, iy;
     flx[r] = floor_cell(sx[r], ix);
     fly[r] = floor_cell(sy[r], iy);
-    const int xa = clampi(x + ix, 0, w - 1), xb = clampi(x + ix + 1, 0, w - 1);
-    const int ya = __mul24(clampi(y0 + r + iy, 0, h - 1), w), yb = __mul24(clampi(y0 + r + iy + 1, 0, h - 1), w);
-    taps[r][0] = tb.f32(ya + xa);
-    taps[r][1] = tb.f32(ya + xb);
-    taps[r][2] = tb.f32(yb + xa);
-    taps[r][3] = tb.f32(yb + xb);
+    // the cell clamped to [-1, w-1] x [-1, h-1], offset by the border: the
+    // four taps are o, o + 1, o + pitch, o + pitch + 1
+    const int o = __mul24(clampi(y0 + r + iy + 1, 0, h), pitch) + clampi(x + ix + 1, 0, w);
+    taps[r][0] = tb.f32(o, 0);
+    taps[r][1] = tb.f32(o, 1);
+    taps[r][2] = tb.f32(o, pitch);
+    taps[r][3] = tb.f32(o, pitch + 1);
   };
 #pragma unroll
   for (int r = 0; r < kAhead; ++r) gather(r);
   __builtin_amdgcn_sched_barrier(0);
 
-  double acc = 0.0;
-  float upx = hux, upy = huy;   // old value of the row above
+  double accR = 0.0, accG = 0.0;
+  // c - u of a row is -(c - d) of the row above (both from the old state;
+  // IEEE subtraction is antisymmetric, so the negation is exact)
+  double nux = 0.0, nuy = 0.0;
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
     if (r + kAhead < RPT) gather(r + kAhead);
@@ -154,21 +158,21 @@ __device__ __forceinline__ double resident_step(const ResidentTile& P, float (&s
     const float lx = from_left(sx[r], ex), ly = from_left(sy[r], ey);
     const float rx = from_right(sx[r], ex), ry = from_right(sy[r], ey);
     const float dx = r == RPT - 1 ? hdx : sx[r + 1], dy = r == RPT - 1 ? hdy : sy[r + 1];
-    const float cxs = sx[r], cys = sy[r];
-    const double cx = cxs, cy = cys;
-    double e, gx, gy;
-    pixel_eval(cx - (double)flx[r], cy - (double)fly[r], taps[r][0], taps[r][1], taps[r][2], taps[r][3], rr[r],
-               cx, cy, lx, ly, rx, ry,
-               upx, upy, dx, dy, P.lam, e, gx, gy);
-    acc += e;
+    const double cx = sx[r], cy = sy[r];
+    const double uxd = r == 0 ? cx - (double)hux : -nux, uyd = r == 0 ? cy - (double)huy : -nuy;
+    const double dxd = cx - (double)dx, dyd = cy - (double)dy;
+    double gx, gy;
+    pixel_eval_d(cx - (double)flx[r], cy - (double)fly[r], taps[r][0], taps[r][1], taps[r][2], taps[r][3], rr[r],
+                 cx - (double)lx, cx - (double)rx, uxd, dxd, cy - (double)ly, cy - (double)ry, uyd, dyd, P.lam,
+                 accR, accG, gx, gy);
+    nux = dxd;
+    nuy = dyd;
     sx[r] = gd_update<float>(cx, gx, P.tau);
     sy[r] = gd_update<float>(cy, gy, P.tau);
     // pin the row's results here: without this the compiler sinks the
     // energy and update arithmetic of all rows to the end of the iteration,
     // keeping every row's intermediates live at once
-    asm volatile("" : "+v"(acc), "+v"(sx[r]), "+v"(sy[r]));
-    upx = cxs;
-    upy = cys;
+    asm volatile("" : "+v"(accR), "+v"(accG), "+v"(sx[r]), "+v"(sy[r]));
     __builtin_amdgcn_sched_barrier(0);
   }
 
@@ -185,7 +189,7 @@ __device__ __forceinline__ double resident_step(const ResidentTile& P, float (&s
     }
     store_columns<RPT>(P, sx, sy, cnext, lane);
   }
-  return acc;
+  return lane_energy(accR, accG, P.lam);
 }
 
 }  // namespace rs

@@ -201,7 +201,8 @@ __device__ bool level_resident(const SolveArgs& a, const LevelView<float>& V, fl
   P.ntx = ntx;
   P.tau = V.tau;
   P.lam = V.lam;
-  const ReadBuf tb(V.T), rb(V.R);
+  P.pitch = V.pitch;
+  const ReadBuf tb(V.T - V.pitch - 1), rb(V.R);   // T from its border element (-1, -1)
   float sx[RPT], sy[RPT];
   float* colx0 = slot + a.colx_off;
   float* colx1 = colx0 + a.colx_stride;
@@ -316,10 +317,11 @@ __device__ bool run_task(const SolveArgs& a, const TaskDesc& d, Group& G, float*
       cur = dst;
     }
     LevelView<float> V;
-    V.R = a.pyr[l] + (size_t)d.ref * n;
-    V.T = a.pyr[l] + (size_t)d.tmpl * n;
+    V.R = a.pyr[l] + (size_t)d.ref * a.fstride[l];
+    V.T = a.pyr[l] + (size_t)d.tmpl * a.fstride[l];
     V.h = h;
     V.w = w;
+    V.pitch = a.pitch[l];
     V.tau = a.tau;
     V.lam = a.lam;
     const int th = a.thl[l];
@@ -350,7 +352,7 @@ __device__ bool run_task(const SolveArgs& a, const TaskDesc& d, Group& G, float*
       V.u = cur;
       V.out = other;
       double* pp = part + (size_t)par * a.max_tiles;
-      sweep_tiles<float, SW_UPDATE, false>(V, G.member, G.g, th, red, pp, nullptr);
+      sweep_tiles<float, SW_UPDATE, false, true>(V, G.member, G.g, th, red, pp, nullptr);
       if (!group_sync(G, abort_flag, a.spin_limit, s_flag)) return false;
       if (threadIdx.x < kWave) {
         const double E = wave_sum_array(pp, nt, threadIdx.x);
@@ -530,7 +532,7 @@ __global__ void __launch_bounds__(kWG) k_plain_prolong(const float* uc, float* u
 
 __global__ void __launch_bounds__(kWG) k_plain_sweep(LevelView<float> V, int th, double* part) {
   __shared__ double red[kWG / kWave];
-  sweep_tiles<float, SW_UPDATE, false>(V, blockIdx.x, gridDim.x, th, red, part, nullptr);
+  sweep_tiles<float, SW_UPDATE, false, true>(V, blockIdx.x, gridDim.x, th, red, part, nullptr);
 }
 
 __global__ void __launch_bounds__(kWave) k_plain_reduce(const double* part, int n, double* E) {
@@ -588,7 +590,7 @@ hipError_t launch_plain_prolong(const float* uc, float* uf, int h, int w, hipStr
   return hipGetLastError();
 }
 
-hipError_t launch_plain_sweep(const float* R, const float* T, const float* u, float* un, int h, int w,
+hipError_t launch_plain_sweep(const float* R, const float* T, int pitch, const float* u, float* un, int h, int w,
                               double tau, double lam, int th, double* part, hipStream_t s) {
   LevelView<float> V;
   V.R = R;
@@ -597,6 +599,7 @@ hipError_t launch_plain_sweep(const float* R, const float* T, const float* u, fl
   V.out = un;
   V.h = h;
   V.w = w;
+  V.pitch = pitch;
   V.tau = tau;
   V.lam = lam;
   hipLaunchKernelGGL(k_plain_sweep, dim3(tiles_of(h, w, th)), dim3(kWG), 0, s, V, th, part);

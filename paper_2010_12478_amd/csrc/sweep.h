@@ -29,13 +29,19 @@ namespace rs {
 
 enum SweepWrite { SW_NONE = 0, SW_UPDATE = 1, SW_GRAD = 2 };
 
+// One pyramid level of one registration.  R and T point at pixel (0, 0) of
+// rows `pitch` elements apart.  In the solver's padded pyramid (PAD) every
+// level carries a one-pixel replicate border: rows -1 .. h and columns
+// -1 .. w are readable and hold the value of the nearest pixel, so a
+// bilinear cell clamped to [-1, h-1] x [-1, w-1] reads exactly the values the
+// edge-clamped taps would.
 template <typename S>
 struct LevelView {
-  const S* R;   // [h][w]
-  const S* T;   // [h][w]
+  const S* R;   // [h][pitch]
+  const S* T;   // [h][pitch]
   const S* u;   // [2][h][w]
   S* out;       // [2][h][w]: u' (SW_UPDATE) or dE/du (SW_GRAD)
-  int h, w;
+  int h, w, pitch;
   double tau, lam;
 };
 
@@ -53,38 +59,52 @@ __host__ __device__ inline int level_tile_rows(int th0, int l) {
 // One pixel of the fused sweep, everything in double: bilinear sample S of T
 // from the taps i00 (x0, y0), i01 (x0 + 1, y0), i10 (x0, y0 + 1), i11 at the
 // in-cell fractions (fx, fy), with its position derivatives; residual
-// r = S - R; the neighbour values (c = pixel, l/r/u/d = left/right/up/down,
-// the pixel itself where the neighbour lies outside the grid).
+// r = S - R; the differences of the pixel's displacement c to its neighbours
+// (l/r/u/d = left/right/up/down; a neighbour outside the grid is the pixel
+// itself, difference +0):
 //   S     = (1 - fy) ((1 - fx) i00 + fx i01) + fy ((1 - fx) i10 + fx i11)
 //   dS/dx = (1 - fy) (i01 - i00) + fy (i11 - i10)
 //   dS/dy = (1 - fx) (i10 - i00) + fx (i11 - i01)
-//   g     = (2 r) dS/dp + (2 lam) (((c - l) + (c - r)) + (c - u)) + (c - d))
-//   e     = r^2 + lam ((r - c)^2 + (d - c)^2) summed over both components
+//   g     = (2 r) dS/dp + (2 lam) ((((c - l) + (c - r)) + (c - u)) + (c - d))
 // The gradient (and with it every stored iterate) is evaluated without
 // contraction: each product and sum is one rounded float64 operation, in the
 // order written above, so any implementation of these formulas in that
-// order produces the same bits.  The energy only feeds the stopping test and
-// may use fused operations.  Every execution path evaluates a pixel through
-// this function, so they agree bitwise.
-__device__ __forceinline__ void pixel_eval(double fx, double fy, double i00, double i01, double i10, double i11,
-                                           double R, double cx, double cy, double lx, double ly, double rx,
-                                           double ry, double ux, double uy, double dx, double dy, double lam,
-                                           double& e, double& gx, double& gy) {
+// order produces the same bits.  The energy terms r^2 and
+// (r - c)^2 + (d - c)^2 of both components (the forward differences inside
+// the grid) go to the accumulators accR and accG, with fused operations: the
+// energy only feeds the stopping test.  Every execution path evaluates a
+// pixel through this function, so they agree bitwise.
+__device__ __forceinline__ void pixel_eval_d(double fx, double fy, double i00, double i01, double i10, double i11,
+                                             double R, double lxd, double rxd, double uxd, double dxd, double lyd,
+                                             double ryd, double uyd, double dyd, double lam, double& accR,
+                                             double& accG, double& gx, double& gy) {
 #pragma clang fp contract(off)
   const double ox = 1.0 - fx, oy = 1.0 - fy;
   const double s = oy * (ox * i00 + fx * i01) + fy * (ox * i10 + fx * i11);
   const double sx = oy * (i01 - i00) + fy * (i11 - i10);
   const double sy = ox * (i10 - i00) + fx * (i11 - i01);
   const double res = s - R;
-  const double lxd = cx - lx, rxd = cx - rx, uxd = cx - ux, dxd = cx - dx;
-  const double lyd = cy - ly, ryd = cy - ry, uyd = cy - uy, dyd = cy - dy;
   const double nbx = ((lxd + rxd) + uxd) + dxd;
   const double nby = ((lyd + ryd) + uyd) + dyd;
   const double r2 = 2.0 * res, l2 = 2.0 * lam;
   gx = r2 * sx + l2 * nbx;
   gy = r2 * sy + l2 * nby;
-  const double reg = fma(rxd, rxd, fma(dxd, dxd, fma(ryd, ryd, dyd * dyd)));
-  e = fma(res, res, lam * reg);
+  accR = fma(res, res, accR);
+  accG = fma(rxd, rxd, fma(dxd, dxd, fma(ryd, ryd, fma(dyd, dyd, accG))));
+}
+
+// The same from the neighbour values (c = the pixel).
+__device__ __forceinline__ void pixel_eval(double fx, double fy, double i00, double i01, double i10, double i11,
+                                           double R, double cx, double cy, double lx, double ly, double rx,
+                                           double ry, double ux, double uy, double dx, double dy, double lam,
+                                           double& accR, double& accG, double& gx, double& gy) {
+  pixel_eval_d(fx, fy, i00, i01, i10, i11, R, cx - lx, cx - rx, cx - ux, cx - dx, cy - ly, cy - ry, cy - uy,
+               cy - dy, lam, accR, accG, gx, gy);
+}
+
+// A lane's energy over its rows of a tile from its two accumulators.
+__device__ __forceinline__ double lane_energy(double accR, double accG, double lam) {
+  return fma(lam, accG, accR);
 }
 
 // Gradient-descent update of one component, c - tau g (one rounded product,
@@ -118,7 +138,7 @@ struct Unit {
 // and halo loads of unit i + 1, and unit i is computed while those are in
 // flight, so each unit exposes one memory round trip instead of two.
 // Arithmetic is double; the stored type S is float (or double).
-template <typename S, int WRITE, bool GNORM>
+template <typename S, int WRITE, bool GNORM, bool PAD>
 __device__ void sweep_tiles(const LevelView<S>& L, int first, int stride, int th, double* red, double* part,
                             double* gpart) {
   const int h = L.h, w = L.w;
@@ -132,7 +152,9 @@ __device__ void sweep_tiles(const LevelView<S>& L, int first, int stride, int th
   const size_t hw = (size_t)h * w;
   const int ihw = (int)hw;
   const SharedBuf ub(L.u);                          // plane 0 at 0, plane 1 at hw
-  const ReadBuf rb(L.R), tb(L.T);
+  const int pitch = L.pitch;
+  // padded: T addressed from its (-1, -1) element, so every offset is >= 0
+  const ReadBuf rb(L.R), tb(PAD ? L.T - pitch - 1 : L.T);
   const double lam = L.lam, tau = L.tau;
 
   auto setup = [&](int i, Unit<S>& U) {
@@ -157,7 +179,7 @@ __device__ void sweep_tiles(const LevelView<S>& L, int first, int stride, int th
       U.ay[r] = ub.load<S>(ihw + row + xc);
     }
 #pragma unroll
-    for (int r = 0; r < kRB; ++r) U.rr[r] = rb.load<S>(__mul24(min(U.yb + r, h - 1), w) + xc);
+    for (int r = 0; r < kRB; ++r) U.rr[r] = rb.load<S>(__mul24(min(U.yb + r, h - 1), pitch) + xc);
     if (lane == 0 || lane == kWave - 1) {
       // the column outside the tile, clamped to the image: at the image edge
       // it is the pixel's own column, so the missing difference is exactly 0
@@ -172,7 +194,7 @@ __device__ void sweep_tiles(const LevelView<S>& L, int first, int stride, int th
   };
 
   Unit<S> A, B;
-  double accE = 0.0, accG = 0.0;
+  double accR = 0.0, accG = 0.0, accN = 0.0;
   if (n_units > 0) {
     setup(0, A);
     load(A);
@@ -191,12 +213,21 @@ __device__ void sweep_tiles(const LevelView<S>& L, int first, int stride, int th
         flx[r] = floor_cell((float)A.ax[r + 1], ix);
         fly[r] = floor_cell((float)A.ay[r + 1], iy);
         const int x0 = xc + ix, y0 = min(A.yb + r, h - 1) + iy;
-        const int xa = clampi(x0, 0, w - 1), xb = clampi(x0 + 1, 0, w - 1);
-        const int ya = __mul24(clampi(y0, 0, h - 1), w), yb = __mul24(clampi(y0 + 1, 0, h - 1), w);
-        taps[r][0] = tb.load<S>(ya + xa);
-        taps[r][1] = tb.load<S>(ya + xb);
-        taps[r][2] = tb.load<S>(yb + xa);
-        taps[r][3] = tb.load<S>(yb + xb);
+        if constexpr (PAD) {
+          // the cell clamped to [-1, w-1] x [-1, h-1], offset by the border
+          const int o = __mul24(clampi(y0 + 1, 0, h), pitch) + clampi(x0 + 1, 0, w);
+          taps[r][0] = tb.load<S>(o);
+          taps[r][1] = tb.load<S>(o + 1);
+          taps[r][2] = tb.load<S>(o + pitch);
+          taps[r][3] = tb.load<S>(o + pitch + 1);
+        } else {
+          const int xa = clampi(x0, 0, w - 1), xb = clampi(x0 + 1, 0, w - 1);
+          const int ya = __mul24(clampi(y0, 0, h - 1), w), yb = __mul24(clampi(y0 + 1, 0, h - 1), w);
+          taps[r][0] = tb.load<S>(ya + xa);
+          taps[r][1] = tb.load<S>(ya + xb);
+          taps[r][2] = tb.load<S>(yb + xa);
+          taps[r][3] = tb.load<S>(yb + xb);
+        }
       }
     }
     // loads of the next unit, in flight during this unit's arithmetic
@@ -224,12 +255,13 @@ __device__ void sweep_tiles(const LevelView<S>& L, int first, int stride, int th
           rys = A.hy[r];
         }
         const double cx = cxs, cy = cys;
-        double e, gx, gy;
+        double nR = accR, nG = accG, gx, gy;   // accumulated only for pixels inside the grid
         pixel_eval(cx - (double)flx[r], cy - (double)fly[r], taps[r][0], taps[r][1], taps[r][2], taps[r][3],
                    A.rr[r], cx, cy, lxs, lys,
-                   rxs, rys, A.ax[r], A.ay[r], A.ax[r + 2], A.ay[r + 2], lam, e, gx, gy);
+                   rxs, rys, A.ax[r], A.ay[r], A.ax[r + 2], A.ay[r + 2], lam, nR, nG, gx, gy);
         if (vx) {
-          accE += e;
+          accR = nR;
+          accG = nG;
           const int o = __mul24(y, w) + x;
           if (WRITE == SW_UPDATE) {
             L.out[o] = gd_update<S>(cx, gx, tau);
@@ -238,18 +270,19 @@ __device__ void sweep_tiles(const LevelView<S>& L, int first, int stride, int th
             L.out[o] = (S)gx;
             L.out[hw + o] = (S)gy;
           }
-          if (GNORM) accG += gx * gx + gy * gy;
+          if (GNORM) accN += gx * gx + gy * gy;
         }
       }
     }
     if ((i + 1) % upt == 0) {   // last unit of this tile: order-fixed block sums
-      const double E = block_sum(accE, red);
+      const double E = block_sum(lane_energy(accR, accG, lam), red);
       if (threadIdx.x == 0) part[A.tile] = E;
-      accE = 0.0;
+      accR = 0.0;
+      accG = 0.0;
       if (GNORM) {
-        const double G = block_sum(accG, red);
+        const double G = block_sum(accN, red);
         if (threadIdx.x == 0) gpart[A.tile] = G;
-        accG = 0.0;
+        accN = 0.0;
       }
     }
     A = B;
