@@ -44,6 +44,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-dataflow", action="store_true")
+    ap.add_argument("--no-mock", action="store_true", help="skip the mock-operator scan microbenchmarks")
     ap.add_argument("--cpu-sample", type=int, default=0, help="registrations in the oracle sample")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 3 device-to-device copies of MIB MiB (calibrates the HBM byte counters)")
@@ -159,6 +160,35 @@ def _oracle_pair(a):
     R, T, p = a
     r = register(pyramid(R, p.levels), pyramid(T, p.levels), None, p)
     return r.iters
+
+
+def mock_scan_report(rs):
+    """The paper's microbenchmarks (Section 5) on the GPU: 98,304 elements,
+    1024 workers (one wavefront each), operator time 10 us, static or
+    exponential (rate 1/t, independent per application, or per-frame
+    difficulty); every execution form of the scan machinery, device time from
+    HIP events.  Each result is also checked: every prefix (0, e + 1) and no
+    adjacency violation."""
+    import numpy as np
+    M, P, t = 98304, 1024, 10.0
+    want = np.stack([np.zeros(M, np.int64), np.arange(1, M + 1)], axis=1)
+    runs = [("static", "level_static", "lf"), ("static", "segments", "lf"), ("static", "flex", "lf"),
+            ("exp", "level_static", "lf"), ("exp", "level_queued", "lf"), ("exp", "dataflow", "lf"),
+            ("exp", "level_static", "dissemination"), ("exp", "dataflow", "dissemination"),
+            ("exp", "segments", "lf"), ("exp", "flex", "lf"), ("exp", "segments", "dissemination"),
+            ("exp", "flex", "dissemination"),
+            ("frame", "dataflow", "lf"), ("frame", "segments", "lf"), ("frame", "flex", "lf"),
+            ("frame", "segments", "dissemination"), ("frame", "flex", "dissemination")]
+    out = []
+    for dist, form, algo in runs:
+        seg_form = form in ("segments", "flex")
+        prefix, _, counts, ms = rs.scan_mock(M, form, P, t, dist, 1410, "lf" if seg_form else algo, 0, algo)
+        ok = bool(np.array_equal(prefix.cpu().numpy().astype(np.int64), want)) and counts[4] == 0
+        row = {"time": dist, "form": form, "plan": algo, "ms": round(ms[3], 3), "ops": int(counts[3]), "correct": ok}
+        if seg_form:
+            row["phases_ms"] = [round(x, 3) for x in ms[:3]]
+        out.append(row)
+    return {"elements": M, "workers": P, "mean_us": t, "runs": out}
 
 
 def main():
@@ -286,6 +316,8 @@ def main():
                            "ms_per_step": round(1000 * plain_s, 1),
                            "mode": "one registration at a time, one launch per iteration, host energy read-back"}
         result["batched_over_plain"] = round(value / (M / plain_s), 2)
+    if not args.no_mock:
+        result["mock_scan"] = mock_scan_report(rs)
     result["input_generation_s"] = round(gen_s, 2)
     print(json.dumps(result), flush=True)
 

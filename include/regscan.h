@@ -264,6 +264,59 @@ int reg_last_solve_timing(double* total_ms, int* launches);
  * *n.  A replayed graph (SCAN_F_GRAPH) records these events itself. */
 int reg_last_solve_launch_ms(double* ms, int cap, int* n);
 
+/* Prefix scan with an artificial operator (Section 5, microbenchmarks): the
+ * scan machinery of scan_run applied to an operator whose only work is to wait.
+ * A node is the frame range (i, k) it covers, element e = (e, e + 1); the
+ * operator maps (i, j), (j', k) to (i, k), counting a violation if j != j',
+ * after waiting for the operator time of (i, k): t = mean_us for
+ * MOCK_STATIC_TIME, or exponential with rate 1/t for MOCK_EXP_TIME (capped at
+ * 64 t), drawn from the splitmix64 finaliser of the counter
+ * seed + 0x9E3779B97F4A7C15 * (1 + i + 2^32 k), u = top 53 bits / 2^53,
+ * time = -t ln(1 - u); or for MOCK_FRAME_TIME (d_i + d_k) / 2, d_f being that
+ * exponential draw for (f, f) (per-frame difficulty: every application
+ * touching a slow frame is slow).  The same application takes the same time
+ * in every execution form.  One worker is one wavefront.
+ * Execution forms (`mode`):
+ *   MOCK_LEVEL_STATIC  the plan (algo, chunk, global_algo) level by level, one
+ *                      launch per level, op q of a level on worker q mod workers
+ *   MOCK_LEVEL_QUEUED  the same, ops drawn from an atomic ticket per level
+ *   MOCK_DATAFLOW      the plan in one launch, ops started as their inputs
+ *                      complete (device ready queue)
+ *   MOCK_SEGMENTS      reduce-then-scan (Section 4.1) over `workers` static
+ *                      segments [w M / workers, (w + 1) M / workers): each worker
+ *                      folds its segment, the global_algo plan scans the
+ *                      segment totals, each worker rescans its segment
+ *   MOCK_FLEX          the same with flexible segment boundaries
+ *                      (Section 4.3, Algorithm 1): workers start in the middle
+ *                      of their segments (worker 0 at the first element, the
+ *                      last worker at the last) and extend toward whichever
+ *                      neighbour is slower, claiming unprocessed elements
+ *                      from the gap between them with atomics
+ *   M         elements (>= 1)
+ *   workers   1 .. the number of wavefronts that can be resident (>= 2 for
+ *             MOCK_FLEX, <= M for the segment forms)
+ *   prefix    [M][2] int32 DEVICE out: the range computed for element e,
+ *             (0, e + 1) when the scan is correct
+ *   seg       [workers][2] int32 DEVICE out or NULL: final segment [pl, pr] of
+ *             every worker (segment forms)
+ *   counts    HOST [5] out or NULL: operator applications in phase 1, the
+ *             global phase, phase 3, in all (level forms: all in [0] and [3]),
+ *             and adjacency violations (0 when correct)
+ *   ms        HOST [4] out or NULL: durations of phase 1, the global phase,
+ *             phase 3 and their sum (HIP events; level forms: [0] and [3])
+ * Synchronises the stream before returning. */
+enum { MOCK_STATIC_TIME = 0, MOCK_EXP_TIME = 1, MOCK_FRAME_TIME = 2 };
+enum { MOCK_LEVEL_STATIC = 0, MOCK_LEVEL_QUEUED = 1, MOCK_DATAFLOW = 2, MOCK_SEGMENTS = 3, MOCK_FLEX = 4 };
+typedef struct {
+  double mean_us;       /* operator time t in microseconds, 0 .. 1e6 */
+  int32_t dist;         /* MOCK_STATIC_TIME, MOCK_EXP_TIME or MOCK_FRAME_TIME */
+  int32_t pad;
+  uint64_t seed;
+} mock_params_t;
+
+int scan_mock_run(int M, int algo, int chunk, int global_algo, int mode, int workers, const mock_params_t* p,
+                  int32_t* prefix, int32_t* seg, int64_t* counts, double* ms, void* stream);
+
 /* Library tuning.
  *   tile_rows  tile height of the finest pyramid level (multiple of 4, 4..64;
  *              level l uses max(4, tile_rows / 4^l)); it fixes the order in

@@ -12,7 +12,9 @@ Modules
                 Brent-Kung, hierarchical reduce-then-scan) and work formulas
   scan          the series registration executed as a scan
   autodiff      gradients of the warp + energy step w.r.t. both images and u
+  mock          the scan on an artificial operator (microbenchmarks): operator
+                times, expected outputs, simulation of the execution forms
 """
-from . import autodiff, plans, registration, scan
+from . import autodiff, mock, plans, registration, scan
 
-__all__ = ["autodiff", "plans", "registration", "scan"]
+__all__ = ["autodiff", "mock", "plans", "registration", "scan"]

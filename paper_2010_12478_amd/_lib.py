@@ -28,7 +28,7 @@ EXPORTS = (
     "reg_pyramid_energy_backward_f64", "reg_compose", "reg_restrict", "reg_prolong",
     "reg_solve_batch", "scan_plan", "scan_run", "reg_last_solve_timing", "reg_last_solve_launch_ms",
     "reg_set_tuning",
-    "reg_autotune", "reg_release",
+    "reg_autotune", "reg_release", "scan_mock_run",
 )
 
 
@@ -42,6 +42,15 @@ class reg_params_t(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("max_iter", ctypes.c_int32),
                 ("fixed_iter", ctypes.c_int32), ("tau", ctypes.c_double),
                 ("lambda_", ctypes.c_double), ("rel_tol", ctypes.c_double)]
+
+
+class mock_params_t(ctypes.Structure):
+    _fields_ = [("mean_us", ctypes.c_double), ("dist", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("seed", ctypes.c_uint64)]
+
+
+MOCK_DISTS = {"static": 0, "exp": 1, "frame": 2}
+MOCK_MODES = {"level_static": 0, "level_queued": 1, "dataflow": 2, "segments": 3, "flex": 4}
 
 
 class scan_op_t(ctypes.Structure):
@@ -80,6 +89,7 @@ _SIGS = {
     "reg_last_solve_launch_ms": (_I, [ctypes.POINTER(ctypes.c_double), _I, ctypes.POINTER(_I)]),
     "reg_autotune": (_I, [_I, _I, _I, _I, ctypes.POINTER(_I), ctypes.POINTER(_I), _P]),
     "reg_release": (None, []),
+    "scan_mock_run": (_I, [_I, _I, _I, _I, _I, _I, _P, _P, _P, _P, _P, _P]),
 }
 
 

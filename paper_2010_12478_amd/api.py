@@ -7,7 +7,8 @@ import ctypes
 import numpy as np
 import torch
 
-from ._lib import (MODES, SCAN_ALGOS, SCAN_F_GRAPH, check, lib, params_struct)
+from ._lib import (MOCK_DISTS, MOCK_MODES, MODES, SCAN_ALGOS, SCAN_F_GRAPH, check, lib, mock_params_t,
+                   params_struct)
 
 
 def _stream():
@@ -240,6 +241,23 @@ def autotune(H, W, levels, batch):
     tr, mg = ctypes.c_int(0), ctypes.c_int(0)
     check(lib.reg_autotune(H, W, levels, batch, ctypes.byref(tr), ctypes.byref(mg), _stream()))
     return tr.value, mg.value
+
+
+def scan_mock(M, mode, workers, mean_us, dist="exp", seed=1410, algo="lf", chunk=0, global_algo="lf",
+              want_seg=False, device="cuda"):
+    """Prefix scan of M elements with the artificial operator (see scan_mock_run).
+    Returns (prefix [M][2] int32, seg [workers][2] int32 or None,
+    counts [phase 1, global, phase 3, total, violations], ms [phase 1, global,
+    phase 3, total])."""
+    prefix = torch.empty((M, 2), dtype=torch.int32, device=device)
+    seg = torch.empty((workers, 2), dtype=torch.int32, device=device) if want_seg else None
+    counts = (ctypes.c_int64 * 5)()
+    ms = (ctypes.c_double * 4)()
+    p = mock_params_t(float(mean_us), MOCK_DISTS[dist], 0, int(seed))
+    check(lib.scan_mock_run(int(M), SCAN_ALGOS[algo], int(chunk), SCAN_ALGOS[global_algo], MOCK_MODES[mode],
+                            int(workers), ctypes.byref(p), _ptr(prefix), _ptr(seg),
+                            ctypes.cast(counts, ctypes.c_void_p), ctypes.cast(ms, ctypes.c_void_p), _stream()))
+    return prefix, seg, list(counts), list(ms)
 
 
 def release():

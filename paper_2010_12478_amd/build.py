@@ -25,7 +25,7 @@ COMMON = ["-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-result",
 DEVICE = ["-x", "hip", f"--offload-arch={ARCH}", "-ffp-contract=on",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-munsafe-fp-atomics"]
-HIP_SOURCES = ["kernels.hip", "solver.hip"]
+HIP_SOURCES = ["kernels.hip", "solver.hip", "mock.hip"]
 CXX_SOURCES = ["host.cpp", "plan.cpp"]
 
 

@@ -62,7 +62,7 @@ struct State {
   int max_group = 64;
   bool resident = true;
   unsigned spin_limit = 1u << 22;   // ~seconds of polling before the watchdog aborts a run
-  DevBuf pyr, slots, part, ctrl, tasks, nodes, upair, iters, status, misc, lvl, flow;
+  DevBuf pyr, slots, part, ctrl, tasks, nodes, upair, iters, status, misc, lvl, flow, mock;
   double* h_E = nullptr;   // pinned host scalar for the plain path
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
   size_t events_used = 0;
@@ -400,6 +400,67 @@ size_t slot_floats_for(int H, int W, int levels, size_t* lvl_off, size_t* bufB_o
 }  // namespace rs
 
 // ===================================================================== C ABI
+
+// ------------------------------------------------------------ mock scan
+
+namespace {
+
+// Host arrays of a dataflow run over a plan: initial dependency counts (inputs
+// that are op outputs), the initially ready ops, and the consumers of every
+// op output.
+struct Flow {
+  std::vector<int> deps0, ready0, cons_off, cons;
+  int n_ready0 = 0;
+};
+
+Flow plan_flow(const std::vector<PlanOp>& plan, int n_base) {
+  const int n = (int)plan.size();
+  Flow f;
+  f.deps0.assign(n, 0);
+  f.ready0.assign(n, -1);
+  f.cons_off.assign(n + 1, 0);
+  for (const PlanOp& q : plan)
+    for (int in : {q.a, q.b})
+      if (in >= n_base) f.cons_off[in - n_base + 1]++;
+  for (int q = 0; q < n; ++q) f.cons_off[q + 1] += f.cons_off[q];
+  f.cons.assign(f.cons_off[n], 0);
+  std::vector<int> fill(f.cons_off.begin(), f.cons_off.end() - 1);
+  for (int q = 0; q < n; ++q) {
+    for (int in : {plan[q].a, plan[q].b})
+      if (in >= n_base) {
+        f.deps0[q]++;
+        f.cons[fill[in - n_base]++] = q;
+      }
+    if (f.deps0[q] == 0) f.ready0[f.n_ready0++] = q;
+  }
+  return f;
+}
+
+// Node holding the prefix (0, e + 1) of element e under `plan`.
+std::vector<int> final_nodes(const std::vector<PlanOp>& plan, int n_base) {
+  std::vector<int> fin(n_base, -1);
+  fin[0] = 0;
+  for (const PlanOp& q : plan)
+    if (q.i == 0) fin[q.k - 1] = q.out;
+  return fin;
+}
+
+struct MockBuf {
+  char* p;
+  template <typename T>
+  T* take(size_t n) {
+    T* r = (T*)p;
+    p += (n * sizeof(T) + 255) / 256 * 256;
+    return r;
+  }
+};
+
+// Workspace of scan_mock_run (every array rounded up to 256 bytes).
+size_t mock_bytes(size_t n_nodes, size_t n_ops, size_t n_base, size_t n_levels, size_t workers) {
+  return 32 * 256 + n_nodes * 8 + n_ops * 48 + n_base * 4 + (n_levels + 16) * 4 + workers * 40;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -1057,12 +1118,171 @@ int reg_autotune(int H, int W, int levels, int batch, int* tile_rows, int* max_g
   return REG_OK;
 }
 
+int scan_mock_run(int M, int algo, int chunk, int global_algo, int mode, int workers, const mock_params_t* p,
+                  int32_t* prefix, int32_t* seg_out, int64_t* counts, double* ms, void* stream) {
+  std::lock_guard<std::recursive_mutex> lk(g_mu);
+  if (M < 1) return fail(REG_E_INVALID, "M = %d < 1", M);
+  if (!p) return fail(REG_E_INVALID, "params is NULL");
+  if (!(p->mean_us >= 0.0) || !(p->mean_us <= 1e6)) return fail(REG_E_INVALID, "mean_us must be in [0, 1e6]");
+  if (p->dist != MOCK_STATIC_TIME && p->dist != MOCK_EXP_TIME && p->dist != MOCK_FRAME_TIME)
+    return fail(REG_E_INVALID, "unknown dist %d", p->dist);
+  if (mode < MOCK_LEVEL_STATIC || mode > MOCK_FLEX) return fail(REG_E_INVALID, "unknown mode %d", mode);
+  if (!prefix) return fail(REG_E_INVALID, "prefix is NULL");
+  if (workers < 1) return fail(REG_E_INVALID, "workers = %d < 1", workers);
+  const bool segs = mode == MOCK_SEGMENTS || mode == MOCK_FLEX;
+  if (segs && workers > M) return fail(REG_E_INVALID, "%d workers for %d elements", workers, M);
+  if (mode == MOCK_FLEX && workers < 2) return fail(REG_E_INVALID, "work stealing needs >= 2 workers");
+  if (segs && (global_algo < SCAN_SEQ || global_algo > SCAN_BRENT_KUNG))
+    return fail(REG_E_INVALID, "unknown global algorithm %d", global_algo);
+  TRY(ensure_device());
+  int per_cu = 0;
+  HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, mock_worker_kernel(), 64, 0));
+  const int capacity = per_cu * g.n_cu;
+  if (workers > capacity)
+    return fail(REG_E_INVALID, "%d workers exceed the %d wavefronts that can be resident", workers, capacity);
+  int khz = 0;
+  HIPCHK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, g.device));
+  if (khz <= 0) return fail(REG_E_HIP, "wall-clock rate unavailable");
+  hipStream_t s = (hipStream_t)stream;
+
+  // the plan: the whole scan (level modes) or the global phase over the workers
+  std::vector<PlanOp> plan;
+  int n_levels = 0;
+  const int n_base = segs ? workers : M;
+  try {
+    if (rs::build_plan(n_base, segs ? global_algo : algo, segs ? 0 : chunk, global_algo, plan, n_levels) != 0)
+      return fail(REG_E_INVALID, "invalid plan arguments");
+  } catch (const std::exception& e) {
+    return fail(REG_E_INVALID, "plan construction failed: %s", e.what());
+  }
+  const int n_ops = (int)plan.size();
+  const size_t n_nodes = (size_t)n_base + n_ops;
+  TRY(ensure(g.mock, mock_bytes(n_nodes, n_ops, n_base, n_levels, workers)));
+  MockBuf mb{(char*)g.mock.p};
+  int* err = mb.take<int>(8);
+  int2* nodes = mb.take<int2>(n_nodes);
+  MockOp* d_ops = mb.take<MockOp>(n_ops);
+  int* d_fin = mb.take<int>(n_base);
+  int* tickets = mb.take<int>(n_levels + 1);
+  int* deps = mb.take<int>(n_ops);
+  int* ready = mb.take<int>(n_ops);
+  int* flowbuf = mb.take<int>(3 * (size_t)n_ops + 1 + 2 * (size_t)n_ops);   // deps0, ready0, cons_off, cons
+  int* ctrl = mb.take<int>(8);
+  unsigned long long* gaps = mb.take<unsigned long long>(workers);
+  float* rate = mb.take<float>(workers);
+  int2* total = mb.take<int2>(workers);
+  int2* seg = seg_out ? (int2*)seg_out : mb.take<int2>(workers);
+  int2* gpre = mb.take<int2>(workers);
+
+  std::vector<MockOp> hops(n_ops);
+  for (int q = 0; q < n_ops; ++q) hops[q] = {plan[q].out, plan[q].a, plan[q].b, 0};
+  const std::vector<int> fin = final_nodes(plan, n_base);
+  const Flow f = plan_flow(plan, n_base);
+  std::vector<int> flow_host;
+  flow_host.insert(flow_host.end(), f.deps0.begin(), f.deps0.end());
+  flow_host.insert(flow_host.end(), f.ready0.begin(), f.ready0.end());
+  flow_host.insert(flow_host.end(), f.cons_off.begin(), f.cons_off.end());
+  flow_host.insert(flow_host.end(), f.cons.begin(), f.cons.end());
+  std::vector<int> zeros(std::max(8, n_levels + 1), 0);
+  HIPCHK(hipMemcpyAsync(d_ops, hops.data(), n_ops * sizeof(MockOp), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(d_fin, fin.data(), n_base * sizeof(int), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(flowbuf, flow_host.data(), flow_host.size() * sizeof(int), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(err, zeros.data(), 8 * sizeof(int), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(tickets, zeros.data(), (n_levels + 1) * sizeof(int), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(ctrl, zeros.data(), 8 * sizeof(int), hipMemcpyHostToDevice, s));
+  const int* deps0 = flowbuf;
+  const int* ready0 = flowbuf + n_ops;
+  const int* cons_off = flowbuf + 2 * n_ops;
+  const int* cons = flowbuf + 3 * n_ops + 1;
+
+  MockArgs a;
+  a.mean_us = p->mean_us;
+  a.cap_us = std::max(p->mean_us * 64.0, p->mean_us);
+  a.ticks_per_us = khz / 1000.0;
+  a.seed = p->seed;
+  a.dist = p->dist;
+  a.spin_limit = g.spin_limit;
+  a.err = err;
+
+  hipEvent_t ev[4];
+  for (int i = 0; i < 4; ++i) HIPCHK(hipEventCreate(&ev[i]));
+  struct EvGuard {
+    hipEvent_t* e;
+    ~EvGuard() {
+      for (int i = 0; i < 4; ++i) (void)hipEventDestroy(e[i]);
+    }
+  } guard{ev};
+  auto run_plan = [&](int n_workers) -> int {
+    if (mode == MOCK_DATAFLOW || segs) {
+      HIPCHK(launch_mock_dataflow(a, d_ops, n_ops, nodes, deps, deps0, ready, ready0, f.n_ready0, cons_off, cons,
+                                  n_base, ctrl, std::min(n_workers, std::max(n_ops, 1)), s));
+    } else {
+      for (int lvl = 1, first = 0; lvl <= n_levels; ++lvl) {
+        int n = 0;
+        while (first + n < n_ops && plan[first + n].level == lvl) ++n;
+        HIPCHK(launch_mock_level(a, d_ops, first, n, nodes, n_workers, mode == MOCK_LEVEL_QUEUED, tickets + lvl, s));
+        first += n;
+      }
+    }
+    return REG_OK;
+  };
+  int64_t cnt[5] = {0, 0, 0, 0, 0};
+  if (!segs) {
+    HIPCHK(launch_mock_elements(nodes, M, 0, s));
+    HIPCHK(hipEventRecord(ev[0], s));
+    TRY(run_plan(workers));
+    HIPCHK(hipEventRecord(ev[1], s));
+    HIPCHK(hipEventRecord(ev[2], s));
+    HIPCHK(hipEventRecord(ev[3], s));
+    HIPCHK(launch_mock_gather(nodes, d_fin, (int2*)prefix, M, s));
+    cnt[0] = n_ops;
+  } else {
+    HIPCHK(hipEventRecord(ev[0], s));
+    HIPCHK(launch_mock_phase1(a, M, workers, mode == MOCK_FLEX, gaps, rate, total, seg, (int2*)prefix, s));
+    HIPCHK(hipEventRecord(ev[1], s));
+    HIPCHK(hipMemcpyAsync(nodes, total, workers * sizeof(int2), hipMemcpyDeviceToDevice, s));
+    TRY(run_plan(workers));
+    HIPCHK(launch_mock_gather(nodes, d_fin, gpre, workers, s));
+    HIPCHK(hipEventRecord(ev[2], s));
+    HIPCHK(launch_mock_phase3(a, workers, seg, gpre, (int2*)prefix, s));
+    HIPCHK(hipEventRecord(ev[3], s));
+    cnt[0] = M - workers;
+    cnt[1] = n_ops;
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  int h_err[8] = {};
+  HIPCHK(hipMemcpy(h_err, err, sizeof h_err, hipMemcpyDeviceToHost));
+  int h_ctrl[3] = {};
+  if (mode == MOCK_DATAFLOW || segs) HIPCHK(hipMemcpy(h_ctrl, ctrl, sizeof h_ctrl, hipMemcpyDeviceToHost));
+  if (h_ctrl[2]) return fail(REG_E_HIP, "mock scan abandoned by the forward-progress watchdog");
+  if (segs) {
+    int2 s0;
+    HIPCHK(hipMemcpy(&s0, seg, sizeof s0, hipMemcpyDeviceToHost));
+    cnt[2] = M - (s0.y - s0.x + 1);
+  }
+  cnt[3] = cnt[0] + cnt[1] + cnt[2];
+  cnt[4] = h_err[0];
+  if (counts)
+    for (int i = 0; i < 5; ++i) counts[i] = cnt[i];
+  if (ms) {
+    float t01 = 0, t12 = 0, t23 = 0;
+    HIPCHK(hipEventElapsedTime(&t01, ev[0], ev[1]));
+    HIPCHK(hipEventElapsedTime(&t12, ev[1], ev[2]));
+    HIPCHK(hipEventElapsedTime(&t23, ev[2], ev[3]));
+    ms[0] = t01;
+    ms[1] = t12;
+    ms[2] = t23;
+    ms[3] = (double)t01 + t12 + t23;
+  }
+  return REG_OK;
+}
+
 void reg_release(void) {
   std::lock_guard<std::recursive_mutex> lk(g_mu);
   if (!g.init) return;
   (void)hipDeviceSynchronize();
   for (DevBuf* b : {&g.pyr, &g.slots, &g.part, &g.ctrl, &g.tasks, &g.nodes, &g.upair, &g.iters, &g.status,
-                    &g.misc, &g.lvl, &g.flow}) {
+                    &g.misc, &g.lvl, &g.flow, &g.mock}) {
     if (b->p) (void)hipFree(b->p);
     b->p = nullptr;
     b->n = 0;

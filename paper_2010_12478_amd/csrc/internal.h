@@ -62,6 +62,32 @@ struct SolveArgs {
 
 size_t slot_floats_for(int H, int W, int levels, size_t* lvl_off, size_t* bufB_off);
 
+// Mock-operator scan (mock.hip).  A node is the frame range (i, k) as int2.
+struct MockOp {
+  int out, a, b, pad;   // node ids: out = a (.) b
+};
+struct MockArgs {
+  double mean_us;        // operator time t
+  double cap_us;         // longest drawn time
+  double ticks_per_us;   // wall-clock rate
+  unsigned long long seed;
+  int dist;              // 0 static, 1 exponential with rate 1/t
+  unsigned spin_limit;   // ready-queue polls before the watchdog abandons a dataflow run
+  int* err;              // adjacency violations (device counter)
+};
+const void* mock_worker_kernel();
+hipError_t launch_mock_elements(int2* nodes, int n, int first_frame, hipStream_t s);
+hipError_t launch_mock_level(const MockArgs& a, const MockOp* ops, int first, int n, int2* nodes, int workers,
+                             bool queued, int* ticket, hipStream_t s);
+hipError_t launch_mock_dataflow(const MockArgs& a, const MockOp* ops, int n_ops, int2* nodes, int* deps,
+                                const int* deps0, int* ready, const int* ready0, int n_ready0, const int* cons_off,
+                                const int* cons, int n_base, int* ctrl, int workers, hipStream_t s);
+hipError_t launch_mock_phase1(const MockArgs& a, int M, int workers, bool steal, unsigned long long* gaps,
+                              float* rate, int2* total, int2* seg, int2* prefix, hipStream_t s);
+hipError_t launch_mock_phase3(const MockArgs& a, int workers, const int2* seg, const int2* gprefix, int2* prefix,
+                              hipStream_t s);
+hipError_t launch_mock_gather(const int2* nodes, const int* final_node, int2* out, int n, hipStream_t s);
+
 // kernels.hip
 hipError_t launch_restrict(const void* in, void* out, double scale, int B, int H, int W, bool f64, hipStream_t s);
 // Padded pyramid level (see SolveArgs): dst holds N frames of (h + 2) rows of
