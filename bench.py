@@ -45,6 +45,7 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-dataflow", action="store_true")
     ap.add_argument("--no-mock", action="store_true", help="skip the mock-operator scan microbenchmarks")
+    ap.add_argument("--no-flex", action="store_true", help="skip the flexible-segment (Algorithm 1) scan")
     ap.add_argument("--cpu-sample", type=int, default=0, help="registrations in the oracle sample")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 3 device-to-device copies of MIB MiB (calibrates the HBM byte counters)")
@@ -215,8 +216,12 @@ def main():
 
     lib_path = os.path.join(ROOT, "paper_2010_12478_amd", "libregscan.so")
     if not os.path.exists(lib_path):
-        from paper_2010_12478_amd.build import build
-        build()
+        import importlib.util   # build.py by path: the package needs the library to import
+        spec = importlib.util.spec_from_file_location(
+            "_regscan_build", os.path.join(ROOT, "paper_2010_12478_amd", "build.py"))
+        mod = importlib.util.module_from_spec(spec)
+        spec.loader.exec_module(mod)
+        mod.build()
     import paper_2010_12478_amd as rs
 
     ops, n_levels = rs.plan(M, cfg.algo, cfg.chunk, cfg.global_algo)
@@ -305,6 +310,29 @@ def main():
         result["dataflow"] = {"value": round(M / (mean(ts) / 1000.0), 3), "unit": "frames/s",
                               "ms_per_step": round(mean(ts), 3), "steps": args.steps,
                               "mode": "whole scan in one persistent launch, device ready queue"}
+
+    if not args.no_flex:
+        # the reduce-then-scan with flexible segment boundaries (Algorithm 1)
+        # on as many workers as the hierarchical plan has chunks
+        workers = M // cfg.chunk
+        rs.scan_run_flex(frames, p, workers, cfg.global_algo, want_pairs=False)
+        torch.cuda.synchronize()
+        ts, phases = [], []
+        for _ in range(args.steps):
+            t1 = time.perf_counter()
+            _, _, seg, _, counts, fms = rs.scan_run_flex(frames, p, workers, cfg.global_algo, want_pairs=False)
+            torch.cuda.synchronize()
+            ts.append(1000.0 * (time.perf_counter() - t1))
+            phases.append(fms)
+        result["flex"] = {"value": round(M / (mean(ts) / 1000.0), 3), "unit": "frames/s",
+                          "ms_per_step": round(mean(ts), 3), "steps": args.steps, "workers": workers,
+                          "registrations": int(counts[3]),
+                          "phases_ms": {"pairwise": round(mean([x[0] for x in phases]), 3),
+                                        "phase1": round(mean([x[1] for x in phases]), 3),
+                                        "global_and_rescan": round(mean([x[2] for x in phases]), 3)},
+                          "segment_lengths": sorted(int(s_[1] - s_[0] + 1) for s_ in seg),
+                          "mode": "reduce-then-scan, flexible segment boundaries (Algorithm 1), one group "
+                                  "per worker"}
 
     if not args.no_plain:
         torch.cuda.synchronize()

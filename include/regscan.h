@@ -252,6 +252,41 @@ int scan_run(const float* frames, int N, int H, int W, const reg_params_t* p,
              int algo, int chunk, int global_algo, int mode, int flags,
              float* phi0, float* u_pair, int32_t* op_iters, int32_t* status, void* stream);
 
+/* Register every frame to frame 0 by the reduce-then-scan with flexible
+ * segment boundaries (Section 4.3, Algorithm 1) on `workers` workers, each a
+ * group of workgroups of one persistent launch:
+ *   pairwise  u_pair[k-1] = A(f_{k-1}, f_k), one batch (as scan_run);
+ *   phase 1   worker 0 starts at element 0 and moves right (its partial
+ *             results are the prefixes phi0[e]), the last worker starts at
+ *             element M - 1 and moves left, worker w in between starts at the
+ *             middle of its static segment [w M / workers, (w + 1) M / workers);
+ *             after one step to the right a worker extends its segment toward
+ *             the neighbour with the larger time per registration so far
+ *             (ties: right), or toward the only side with unclaimed elements,
+ *             until both neighbouring gaps are empty; extending right runs
+ *             B(res, x_e), left B(x_e, res);
+ *   global    the global_algo plan (SCAN_SEQ .. SCAN_BRENT_KUNG) over the
+ *             segment totals and then each worker's rescan of its segment from
+ *             the prefix before it, as one dataflow launch planned on the host
+ *             from the final segments.
+ *   frames   [N][H][W], N >= 3;  workers 2 .. N - 1 (one group each, all
+ *            resident)
+ *   phi0     [M][2][H][W] out;  u_pair [M][2][H][W] out or NULL
+ *   seg      HOST [workers][4] out or NULL: pl, pr (the final segment),
+ *            registrations in phase 1, 0
+ *   step     HOST [M] out or NULL: the 1-based phase-1 step at which the
+ *            owning worker absorbed element e (0: a worker's start) - with the
+ *            segments this gives the combination order of every worker
+ *   counts   HOST [4] out or NULL: registrations in phase 1 (M - workers), the
+ *            global plan, the rescans, and in all (with the M pairwise ones)
+ *   ms       HOST [4] out or NULL: pairwise, phase 1, global + rescans (from
+ *            the end of phase 1, including the host round trip that plans
+ *            them), total
+ * Synchronises the stream (phase 1's segments decide the rest). */
+int scan_run_flex(const float* frames, int N, int H, int W, const reg_params_t* p, int workers, int global_algo,
+                  float* phi0, float* u_pair, int32_t* seg, int32_t* step, int64_t* counts, double* ms,
+                  void* stream);
+
 /* Kernel-duration probe: total device time in milliseconds of the persistent
  * solve launches of the last scan_run / reg_solve_batch in REG_BATCHED mode
  * (HIP events recorded around every launch on the launch stream), and the

@@ -88,3 +88,96 @@ def run_scan(frames, params, algo="seq", chunk=0, global_algo="lf", workers=1,
 
 def host_cores():
     return len(os.sched_getaffinity(0))
+
+
+# ------------------------------------------------ flexible segment boundaries
+
+def flex_start(M, workers, w):
+    """Algorithm 1's starting element of worker w (Section 4.3): the first
+    element for worker 0, the last for the last worker, otherwise the middle
+    of the static segment [w M / workers, (w + 1) M / workers)."""
+    if w == 0:
+        return 0
+    if w == workers - 1:
+        return M - 1
+    s0, s1 = w * M // workers, (w + 1) * M // workers
+    return (s0 + s1 - 1) // 2
+
+
+def flex_orders(seg, step, M):
+    """Per worker, the elements absorbed after its start in the order they
+    were absorbed (step 1, 2, ...); checks that the schedule is one the
+    algorithm can produce: segments tile [0, M) in worker order, each holds
+    its worker's start (step 0), every step extends the segment by the
+    adjacent element, and the first step goes right when it can."""
+    workers = len(seg)
+    orders = []
+    for w in range(workers):
+        pl, pr = int(seg[w][0]), int(seg[w][1])
+        if w == 0 and pl != 0 or w == workers - 1 and pr != M - 1:
+            raise ValueError("segments do not cover the series")
+        if w > 0 and int(seg[w - 1][1]) + 1 != pl:
+            raise ValueError(f"segments {w - 1} and {w} are not adjacent")
+        start = flex_start(M, workers, w)
+        if not pl <= start <= pr or step[start] != 0:
+            raise ValueError(f"worker {w} did not start at element {start}")
+        rest = sorted((int(step[e]), e) for e in range(pl, pr + 1) if e != start)
+        if [s for s, _ in rest] != list(range(1, len(rest) + 1)):
+            raise ValueError(f"worker {w} steps are not 1..{len(rest)}")
+        lo = hi = start
+        for n, (_, e) in enumerate(rest):
+            if e == hi + 1:
+                hi = e
+            elif e == lo - 1:
+                lo = e
+            else:
+                raise ValueError(f"worker {w} absorbed non-adjacent element {e}")
+            if n == 0 and w < workers - 1 and e != start + 1:
+                raise ValueError(f"worker {w} did not step right first")
+        orders.append((start, [e for _, e in rest]))
+    return orders
+
+
+def run_flex_scan(frames, params, seg, step, global_algo="lf", pyrs=None):
+    """The reduce-then-scan over flexible segments in the combination order a
+    run recorded (segments and per-element steps): each worker's segment
+    reduced from its start outward (B(res, x_e) to the right, B(x_e, res) to
+    the left; worker 0's partial results are the prefixes), the global plan
+    over the segment totals, then each later segment rescanned from the prefix
+    before it.  Every value is computed here from the frames."""
+    N = len(frames)
+    M = N - 1
+    if pyrs is None:
+        pyrs = frame_pyramids(frames, params.levels)
+    orders = flex_orders(seg, step, M)
+    A = [op_A(pyrs, i, params).u for i in range(M)]
+    phi0 = [None] * M
+    phi0[0] = A[0]
+    totals = []
+    for w, (start, order) in enumerate(orders):
+        res, lo, hi = A[start], start, start
+        for e in order:
+            if e == hi + 1:
+                res = op_B(pyrs, lo, e + 1, res, A[e], params).u
+                hi = e
+                if w == 0:
+                    phi0[e] = res
+            else:
+                res = op_B(pyrs, e, hi + 1, A[e], res, params).u
+                lo = e
+        totals.append(res)
+    workers = len(orders)
+    ops, _ = plans.make_plan(workers, global_algo)
+    node = {w: totals[w] for w in range(workers)}
+    for r in ops:
+        i, k = int(r[4]), int(r[6])
+        u = op_B(pyrs, int(seg[i][0]), int(seg[k - 1][1]) + 1, node[int(r[2])], node[int(r[3])], params).u
+        node[int(r[1])] = u
+        if i == 0:
+            phi0[int(seg[k - 1][1])] = u
+    for w in range(1, workers):
+        cur = phi0[int(seg[w][0]) - 1]
+        for e in range(int(seg[w][0]), int(seg[w][1])):
+            cur = op_B(pyrs, 0, e + 1, cur, A[e], params).u
+            phi0[e] = cur
+    return np.stack(phi0), np.stack(A)

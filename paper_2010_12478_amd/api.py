@@ -215,6 +215,29 @@ def scan_run(frames, params, algo="seq", chunk=0, global_algo="lf", mode="batche
     return out["phi0"], out["u_pair"], out["iters"], out["status"]
 
 
+def scan_run_flex(frames, params, workers, global_algo="lf", want_pairs=True):
+    """Reduce-then-scan with flexible segment boundaries (Algorithm 1).
+    Returns (phi0, u_pair or None, seg [workers][4] int32 numpy, step [M]
+    int32 numpy, counts [phase 1, global, rescans, all], ms [pairwise, phase 1,
+    global + rescans, total])."""
+    _need(frames, "frames")
+    N, H, W = frames.shape
+    M = N - 1
+    dev = frames.device
+    phi0 = torch.empty((M, 2, H, W), dtype=torch.float32, device=dev)
+    u_pair = torch.empty((M, 2, H, W), dtype=torch.float32, device=dev) if want_pairs else None
+    seg = np.zeros((workers, 4), dtype=np.int32)
+    step = np.zeros(M, dtype=np.int32)
+    counts = (ctypes.c_int64 * 4)()
+    ms = (ctypes.c_double * 4)()
+    p = params_struct(params)
+    check(lib.scan_run_flex(_ptr(frames), N, H, W, ctypes.byref(p), int(workers), SCAN_ALGOS[global_algo],
+                            _ptr(phi0), _ptr(u_pair), seg.ctypes.data_as(ctypes.c_void_p),
+                            step.ctypes.data_as(ctypes.c_void_p), ctypes.cast(counts, ctypes.c_void_p),
+                            ctypes.cast(ms, ctypes.c_void_p), _stream()))
+    return phi0, u_pair, seg, step, list(counts), list(ms)
+
+
 def last_solve_timing():
     """(total ms, launches) of the persistent launches of the last batched call."""
     ms, n = ctypes.c_double(0), ctypes.c_int(0)

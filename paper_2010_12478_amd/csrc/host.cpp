@@ -63,6 +63,7 @@ struct State {
   bool resident = true;
   unsigned spin_limit = 1u << 22;   // ~seconds of polling before the watchdog aborts a run
   DevBuf pyr, slots, part, ctrl, tasks, nodes, upair, iters, status, misc, lvl, flow, mock;
+  DevBuf flexw, flexn, flext, flexf;   // flexible-segment scan: worker state, pool, tasks, flow
   double* h_E = nullptr;   // pinned host scalar for the plain path
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
   size_t events_used = 0;
@@ -400,6 +401,35 @@ size_t slot_floats_for(int H, int W, int levels, size_t* lvl_off, size_t* bufB_o
 }  // namespace rs
 
 // ===================================================================== C ABI
+
+// Dependency lists -> the dataflow arrays of run_dataflow: per task the
+// number of inputs produced by other tasks, the initially ready tasks, and the
+// consumers of every task.
+struct TaskFlow {
+  std::vector<int> host;   // deps0 [T], ready0 [T], cons_off [T + 1], cons
+  int n_ready0 = 0;
+};
+
+TaskFlow task_flow(const std::vector<std::vector<int>>& deps) {
+  const int T = (int)deps.size();
+  TaskFlow f;
+  std::vector<int> deps0(T), ready0(T, -1), cons_off(T + 1, 0), cons;
+  for (int t = 0; t < T; ++t) {
+    deps0[t] = (int)deps[t].size();
+    for (int d : deps[t]) cons_off[d + 1]++;
+    if (deps0[t] == 0) ready0[f.n_ready0++] = t;
+  }
+  for (int t = 0; t < T; ++t) cons_off[t + 1] += cons_off[t];
+  cons.assign(cons_off[T], 0);
+  std::vector<int> fill(cons_off.begin(), cons_off.end() - 1);
+  for (int t = 0; t < T; ++t)
+    for (int d : deps[t]) cons[fill[d]++] = t;
+  f.host = deps0;
+  f.host.insert(f.host.end(), ready0.begin(), ready0.end());
+  f.host.insert(f.host.end(), cons_off.begin(), cons_off.end());
+  f.host.insert(f.host.end(), cons.begin(), cons.end());
+  return f;
+}
 
 // ------------------------------------------------------------ mock scan
 
@@ -1118,6 +1148,246 @@ int reg_autotune(int H, int W, int levels, int batch, int* tile_rows, int* max_g
   return REG_OK;
 }
 
+int scan_run_flex(const float* frames, int N, int H, int W, const reg_params_t* p, int workers, int global_algo,
+                  float* phi0, float* u_pair, int32_t* seg_out, int32_t* step_out, int64_t* counts, double* ms,
+                  void* stream) {
+  std::lock_guard<std::recursive_mutex> lk(g_mu);
+  TRY(check_dims(1, H, W));
+  TRY(check_params(p, H, W));
+  if (N < 3) return fail(REG_E_INVALID, "a flexible-segment scan needs N >= 3 frames (got %d)", N);
+  const int M = N - 1;
+  if (workers < 2 || workers > M) return fail(REG_E_INVALID, "workers %d not in [2, %d]", workers, M);
+  if (global_algo < SCAN_SEQ || global_algo > SCAN_BRENT_KUNG)
+    return fail(REG_E_INVALID, "unknown global algorithm %d", global_algo);
+  if (!frames || !phi0) return fail(REG_E_INVALID, "NULL pointer");
+  TRY(ensure_device());
+  hipStream_t s = (hipStream_t)stream;
+  const int L = p->levels;
+  const size_t nf = (size_t)2 * H * W;
+  const int slots = g.blocks_per_cu * g.n_cu;
+  const int groups = (workers + 7) / 8 * 8;
+  if (groups > slots) return fail(REG_E_INVALID, "%d workers exceed the %d resident workgroups", workers, slots);
+  int gs = group_size(workers, H, W, false);
+  while (gs > 1 && (long long)groups * gs > slots) gs /= 2;
+
+  float* pair = u_pair;
+  if (!pair) {
+    TRY(ensure(g.upair, (size_t)M * nf * sizeof(float)));
+    pair = (float*)g.upair.p;
+  }
+  // worker state
+  const size_t ws_bytes = 256 * 16 + (size_t)workers * (8 + 4 + 4 + 16) + (size_t)M * (4 + 4 * L + 4) +
+                          (size_t)workers * 64 + (size_t)workers * 2 * nf * sizeof(float);
+  TRY(ensure(g.flexw, ws_bytes));
+  MockBuf mb{(char*)g.flexw.p};
+  unsigned long long* gaps = mb.take<unsigned long long>(workers);
+  float* rates = mb.take<float>(workers);
+  int* starts = mb.take<int>(workers);
+  int* seg = mb.take<int>(4 * (size_t)workers);
+  int* step = mb.take<int>(M);
+  int* eiters = mb.take<int>((size_t)M * L);
+  int* estatus = mb.take<int>(M);
+  unsigned long long* desc = mb.take<unsigned long long>(8 * (size_t)workers);
+  float* fbuf = mb.take<float>((size_t)workers * 2 * nf);
+
+  std::vector<int> hstart(workers);
+  for (int w = 0; w < workers; ++w) {
+    const int s0 = (int)((long long)w * M / workers), s1 = (int)((long long)(w + 1) * M / workers);
+    hstart[w] = w == 0 ? 0 : w == workers - 1 ? M - 1 : (s0 + s1 - 1) / 2;
+  }
+  std::vector<unsigned long long> hgap(workers, 0);
+  for (int w = 0; w + 1 < workers; ++w)
+    hgap[w] = (unsigned long long)(unsigned)(hstart[w] + 1) | ((unsigned long long)(unsigned)(hstart[w + 1] - 1) << 32);
+  std::vector<float> hrate(workers, 0.f);
+  std::vector<int> hzero(M, 0);
+  HIPCHK(hipMemcpyAsync(gaps, hgap.data(), workers * sizeof(unsigned long long), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(rates, hrate.data(), workers * sizeof(float), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(starts, hstart.data(), workers * sizeof(int), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(step, hzero.data(), M * sizeof(int), hipMemcpyHostToDevice, s));
+
+  hipEvent_t ev[4];
+  for (int i = 0; i < 4; ++i) HIPCHK(hipEventCreate(&ev[i]));
+  struct EvGuard {
+    hipEvent_t* e;
+    ~EvGuard() {
+      for (int i = 0; i < 4; ++i) (void)hipEventDestroy(e[i]);
+    }
+  } guard{ev};
+
+  // pairwise registrations, one batch
+  Pyr P;
+  TRY(build_pyramid(frames, N, H, W, L, P, s));
+  SolveArgs a = base_args(P, H, W, p);
+  std::vector<TaskDesc> tasks(M);
+  for (int k = 1; k <= M; ++k) {
+    TaskDesc& d = tasks[k - 1];
+    d.ref = k - 1;
+    d.tmpl = k;
+    d.kind = 0;
+    d.pad = 0;
+    d.ua = d.ub = nullptr;
+    d.out = pair + (size_t)(k - 1) * nf;
+    d.iters = nullptr;
+    d.status = nullptr;
+  }
+  TRY(upload_tasks(g.tasks, tasks, s));
+  HIPCHK(hipEventRecord(ev[0], s));
+  TRY(run_batched(a, (const TaskDesc*)g.tasks.p, M, s, false));
+  HIPCHK(launch_copy(pair, phi0, nf, s));   // phi_{0,1} = u_{0,1}
+  HIPCHK(hipEventRecord(ev[1], s));
+
+  // phase 1: flexible segments, one group per worker
+  {
+    SolveArgs f = a;
+    const int ctrl_ints = kCtrlHead + kCtrlGroup * groups;
+    TRY(ensure(g.ctrl, (size_t)ctrl_ints * sizeof(int)));
+    f.max_tiles = std::max(f.max_tiles, gs);
+    TRY(ensure(g.part, (size_t)groups * 3 * f.max_tiles * sizeof(double)));
+    TRY(ensure(g.slots, (size_t)groups * f.slot_floats * sizeof(float)));
+    f.tasks = nullptr;
+    f.n_tasks = 0;
+    f.g = gs;
+    f.ctrl = (int*)g.ctrl.p;
+    f.part = (double*)g.part.p;
+    f.ws = (float*)g.slots.p;
+    f.flex = 1;
+    f.flex_workers = workers;
+    f.flex_M = M;
+    f.gaps = gaps;
+    f.rates = rates;
+    f.starts = starts;
+    f.flex_buf = fbuf;
+    f.elem = pair;
+    f.phi0 = phi0;
+    f.flex_seg = seg;
+    f.elem_step = step;
+    f.elem_iters = eiters;
+    f.elem_status = estatus;
+    f.flex_desc = desc;
+    HIPCHK(launch_reset_ctrl(f.ctrl, ctrl_ints, s));
+    HIPCHK(launch_persistent(f, groups * gs, s));
+  }
+  HIPCHK(hipEventRecord(ev[2], s));
+  std::vector<int> hseg(4 * (size_t)workers);
+  HIPCHK(hipMemcpyAsync(hseg.data(), seg, hseg.size() * sizeof(int), hipMemcpyDeviceToHost, s));
+  std::vector<int> hstep(M);
+  HIPCHK(hipMemcpyAsync(hstep.data(), step, M * sizeof(int), hipMemcpyDeviceToHost, s));
+  int h_abort = 0;
+  HIPCHK(hipMemcpyAsync(&h_abort, (int*)g.ctrl.p + 1, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (h_abort) return fail(REG_E_HIP, "phase 1 abandoned by the forward-progress watchdog");
+  for (int w = 0; w < workers; ++w) {
+    const int pl = hseg[4 * w], pr = hseg[4 * w + 1];
+    if (pl > pr || (w == 0 && pl != 0) || (w + 1 == workers && pr != M - 1) ||
+        (w > 0 && hseg[4 * (w - 1) + 1] + 1 != pl))
+      return fail(REG_E_HIP, "phase 1 left an invalid segment %d: [%d, %d]", w, pl, pr);
+  }
+
+  // global scan of the segment totals and the rescans, one dataflow launch
+  std::vector<PlanOp> plan;
+  int n_levels = 0;
+  if (rs::build_plan(workers, global_algo, 0, global_algo, plan, n_levels) != 0)
+    return fail(REG_E_INVALID, "invalid global plan");
+  const int n2 = (int)plan.size();
+  auto pl_of = [&](int w) { return hseg[4 * w]; };
+  auto pr_of = [&](int w) { return hseg[4 * w + 1]; };
+  std::vector<const float*> node(workers + n2, nullptr);
+  for (int w = 0; w < workers; ++w) {
+    const int ops = hseg[4 * w + 2];
+    if (ops == 0) node[w] = pair + (size_t)hstart[w] * nf;
+    else if (w == 0) node[w] = phi0 + (size_t)pr_of(0) * nf;
+    else node[w] = fbuf + ((size_t)w * 2 + ((ops - 1) & 1)) * nf;
+  }
+  int n_pool = 0;
+  for (const PlanOp& q : plan)
+    if (q.i != 0) ++n_pool;
+  TRY(ensure(g.flexn, std::max<size_t>(1, (size_t)n_pool) * nf * sizeof(float)));
+  std::vector<TaskDesc> t2;
+  std::vector<std::vector<int>> dep;
+  std::vector<int> prefix_task(workers, -1);   // task producing phi0[pr_w] (prefix over segments 0..w)
+  int pool = 0;
+  for (int n = 0; n < n2; ++n) {
+    const PlanOp& q = plan[n];
+    TaskDesc d;
+    d.ref = pl_of(q.i);
+    d.tmpl = pr_of(q.k - 1) + 1;
+    d.kind = 1;
+    d.pad = 0;
+    d.ua = node[q.a];
+    d.ub = node[q.b];
+    float* out = q.i == 0 ? phi0 + (size_t)pr_of(q.k - 1) * nf : (float*)g.flexn.p + (size_t)pool++ * nf;
+    d.out = out;
+    d.iters = nullptr;
+    d.status = nullptr;
+    node[q.out] = out;
+    if (q.i == 0) prefix_task[q.k - 1] = n;
+    std::vector<int> dl;
+    for (int in : {q.a, q.b})
+      if (in >= workers) dl.push_back(in - workers);
+    t2.push_back(d);
+    dep.push_back(dl);
+  }
+  int n3 = 0;
+  for (int w = 1; w < workers; ++w) {
+    int prev = prefix_task[w - 1];   // -1: phi0[pl_w - 1] exists already (worker 0)
+    for (int e = pl_of(w); e < pr_of(w); ++e) {
+      TaskDesc d;
+      d.ref = 0;
+      d.tmpl = e + 1;
+      d.kind = 1;
+      d.pad = 0;
+      d.ua = phi0 + (size_t)(e - 1) * nf;
+      d.ub = pair + (size_t)e * nf;
+      d.out = phi0 + (size_t)e * nf;
+      d.iters = nullptr;
+      d.status = nullptr;
+      std::vector<int> dl;
+      if (prev >= 0) dl.push_back(prev);
+      prev = (int)t2.size();
+      t2.push_back(d);
+      dep.push_back(dl);
+      ++n3;
+    }
+  }
+  const int T = (int)t2.size();
+  if (T > 0) {
+    const TaskFlow tf = task_flow(dep);
+    TRY(upload_tasks(g.flext, t2, s));
+    TRY(ensure(g.flexf, (tf.host.size() + 2 * (size_t)T) * sizeof(int)));
+    HIPCHK(hipMemcpyAsync(g.flexf.p, tf.host.data(), tf.host.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    int* fl = (int*)g.flexf.p;
+    int* deps = fl + tf.host.size();
+    TRY(run_dataflow(a, (const TaskDesc*)g.flext.p, T, deps, fl, deps + T, fl + T, tf.n_ready0, fl + 2 * T,
+                     fl + 3 * T + 1, s, false));
+  }
+  HIPCHK(hipEventRecord(ev[3], s));
+  HIPCHK(hipStreamSynchronize(s));
+  int h_abort2 = 0;
+  HIPCHK(hipMemcpy(&h_abort2, (int*)g.ctrl.p + 1, sizeof(int), hipMemcpyDeviceToHost));
+  if (h_abort2) return fail(REG_E_HIP, "global phase abandoned by the forward-progress watchdog");
+  if (seg_out)
+    for (size_t i = 0; i < hseg.size(); ++i) seg_out[i] = hseg[i];
+  if (step_out)
+    for (int e = 0; e < M; ++e) step_out[e] = hstep[e];
+  if (counts) {
+    counts[0] = M - workers;
+    counts[1] = n2;
+    counts[2] = n3;
+    counts[3] = M + (M - workers) + n2 + n3;
+  }
+  if (ms) {
+    float t01 = 0, t12 = 0, t23 = 0;
+    HIPCHK(hipEventElapsedTime(&t01, ev[0], ev[1]));
+    HIPCHK(hipEventElapsedTime(&t12, ev[1], ev[2]));
+    HIPCHK(hipEventElapsedTime(&t23, ev[2], ev[3]));
+    ms[0] = t01;
+    ms[1] = t12;
+    ms[2] = t23;
+    ms[3] = (double)t01 + t12 + t23;
+  }
+  return REG_OK;
+}
+
 int scan_mock_run(int M, int algo, int chunk, int global_algo, int mode, int workers, const mock_params_t* p,
                   int32_t* prefix, int32_t* seg_out, int64_t* counts, double* ms, void* stream) {
   std::lock_guard<std::recursive_mutex> lk(g_mu);
@@ -1282,7 +1552,7 @@ void reg_release(void) {
   if (!g.init) return;
   (void)hipDeviceSynchronize();
   for (DevBuf* b : {&g.pyr, &g.slots, &g.part, &g.ctrl, &g.tasks, &g.nodes, &g.upair, &g.iters, &g.status,
-                    &g.misc, &g.lvl, &g.flow, &g.mock}) {
+                    &g.misc, &g.lvl, &g.flow, &g.mock, &g.flexw, &g.flexn, &g.flext, &g.flexf}) {
     if (b->p) (void)hipFree(b->p);
     b->p = nullptr;
     b->n = 0;

@@ -58,6 +58,22 @@ struct SolveArgs {
   int* ready;
   const int* cons_off;
   const int* cons;
+  // phase 1 of the reduce-then-scan with flexible segment boundaries
+  // (flex != 0, Algorithm 1): group w is worker w of flex_workers
+  int flex;
+  int flex_workers;
+  int flex_M;                 // elements
+  unsigned long long* gaps;   // [workers - 1]: unclaimed elements (lo, hi) between w and w + 1
+  float* rates;               // [workers]: time per registration so far
+  const int* starts;          // [workers]: first element of every worker
+  float* flex_buf;            // [workers][2][2][H][W]: a worker's running result, ping-pong
+  const float* elem;          // [M][2][H][W]: the elements u_{e,e+1}
+  float* phi0;                // [M][2][H][W]: worker 0 writes its partial results (prefixes) here
+  int* flex_seg;              // [workers][4] out: pl, pr, applications, -
+  int* elem_step;             // [M] out: 1-based step at which the element was absorbed (0: a start)
+  int* elem_iters;            // [M][levels] out: iterations of that registration
+  int* elem_status;           // [M] out
+  unsigned long long* flex_desc;   // [workers][8]: descriptor broadcast from a worker's leader
 };
 
 size_t slot_floats_for(int H, int W, int levels, size_t* lvl_off, size_t* bufB_off);

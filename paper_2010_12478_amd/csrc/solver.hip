@@ -411,6 +411,135 @@ __device__ int next_task(const SolveArgs& a, int* queue, int* abort_flag) {
   }
 }
 
+static_assert(sizeof(TaskDesc) == 56, "TaskDesc is broadcast as 7 words");
+
+// Phase 1 with flexible segment boundaries (Algorithm 1, Section 4.3) for
+// group w = worker w.  The leader (member 0, thread 0) keeps the worker's
+// state: the segment [pl, pr] it has absorbed and where its running result
+// lies.  Worker 0 starts at element 0 and only moves right (its partial
+// results are the prefixes, written to phi0); the last worker starts at the
+// last element and only moves left; the others start in the middle of their
+// static segment.  After one step to the right a worker extends toward the
+// neighbour whose time per registration is larger (ties: right), or toward
+// the only side with unclaimed elements; it claims the element next to its
+// segment from the gap (one 64-bit word (lo, hi) per pair of neighbours,
+// compare-and-swap) and the group runs B(res, x_e) or B(x_e, res).  The leader
+// broadcasts each registration's descriptor through agent-scope atomics; the
+// members read it after the group barrier and invalidate their L1 before
+// reading fields another step of the group wrote.
+__device__ int flex_claim(unsigned long long* gaps, int gi, bool from_left) {
+  unsigned long long g = __hip_atomic_load(gaps + gi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  for (;;) {
+    const int lo = (int)(g & 0xffffffffu), hi = (int)(g >> 32);
+    if (lo > hi) return -1;
+    const unsigned long long nw = from_left ? (unsigned long long)(unsigned)(lo + 1) | ((unsigned long long)(unsigned)hi << 32)
+                                            : (unsigned long long)(unsigned)lo | ((unsigned long long)(unsigned)(hi - 1) << 32);
+    if (__hip_atomic_compare_exchange_strong(gaps + gi, &g, nw, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT))
+      return from_left ? lo : hi;
+  }
+}
+
+__device__ __forceinline__ int flex_gap_size(const unsigned long long* gaps, int gi) {
+  const unsigned long long g =
+      __hip_atomic_load((unsigned long long*)gaps + gi, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return (int)(g >> 32) - (int)(g & 0xffffffffu) + 1;
+}
+
+__device__ void flex_phase1(const SolveArgs& a, Group& G, float* slot, double* part, int& par, double* red,
+                            double* s_E, int* s_flag, float2* roll) {
+  int* abort_flag = a.ctrl + 1;
+  const int w = G.id, P = a.flex_workers;
+  if (w >= P) return;   // groups are launched in multiples of 8: the surplus has no segment
+  const size_t nf = (size_t)2 * a.H * a.W;
+  const int L = a.levels;
+  unsigned long long* desc = a.flex_desc + (size_t)w * 8;
+  // leader state
+  int pl = a.starts[w], pr = a.starts[w], ops = 0;
+  unsigned long long t_begin = 0;
+  const bool leader = G.member == 0 && threadIdx.x == 0;
+  if (leader) t_begin = wall_clock64();
+  for (;;) {
+    if (leader) {
+      int e = -1;
+      bool right = true;
+      for (;;) {
+        const int sL = w > 0 ? flex_gap_size(a.gaps, w - 1) : 0;
+        const int sR = w < P - 1 ? flex_gap_size(a.gaps, w) : 0;
+        if (sL <= 0 && sR <= 0) break;
+        if (ops == 0 && sR > 0) right = true;
+        else if (sL > 0 && sR > 0)
+          right = !(__hip_atomic_load(a.rates + w - 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >
+                    __hip_atomic_load(a.rates + w + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        else right = sL <= 0;
+        e = right ? flex_claim(a.gaps, w, true) : flex_claim(a.gaps, w - 1, false);
+        if (e >= 0) break;
+      }
+      int cmd = 0;
+      if (e >= 0) {
+        cmd = 1;
+        const float* res = ops == 0 ? a.elem + (size_t)a.starts[w] * nf
+                           : w == 0 ? a.phi0 + (size_t)pr * nf
+                                    : a.flex_buf + ((size_t)w * 2 + ((ops - 1) & 1)) * nf;
+        float* next = a.flex_buf + ((size_t)w * 2 + (ops & 1)) * nf;
+        TaskDesc d;
+        d.kind = 1;
+        d.pad = 0;
+        if (right) {
+          d.ref = pl;
+          d.tmpl = e + 1;
+          d.ua = res;
+          d.ub = a.elem + (size_t)e * nf;
+          d.out = w == 0 ? a.phi0 + (size_t)e * nf : next;
+        } else {
+          d.ref = e;
+          d.tmpl = pr + 1;
+          d.ua = a.elem + (size_t)e * nf;
+          d.ub = res;
+          d.out = next;
+        }
+        d.iters = a.elem_iters + (size_t)e * L;
+        d.status = a.elem_status + e;
+        unsigned long long words[7];
+        __builtin_memcpy(words, &d, sizeof d);
+        for (int q = 0; q < 7; ++q)
+          __hip_atomic_store(desc + q, words[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        a.elem_step[e] = ops + 1;
+        if (right) pr = e;
+        else pl = e;
+      }
+      __hip_atomic_store(G.task, cmd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (!group_sync(G, abort_flag, a.spin_limit, s_flag)) return;
+    __shared__ int s_cmd;
+    __shared__ unsigned long long s_desc[7];
+    if (threadIdx.x == 0) s_cmd = __hip_atomic_load(G.task, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x < 7) s_desc[threadIdx.x] = __hip_atomic_load(desc + threadIdx.x, __ATOMIC_RELAXED,
+                                                                 __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    if (!s_cmd) break;
+    TaskDesc d;
+    __builtin_memcpy(&d, s_desc, sizeof d);
+    __syncthreads();
+    // the running result was written by this group's previous registration
+    // through other CUs' L1s: drop stale lines before reading it
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (!run_task(a, d, G, slot, part, par, red, s_E, s_flag, roll)) return;
+    if (!group_sync(G, abort_flag, a.spin_limit, s_flag)) return;
+    if (leader) {
+      ++ops;
+      const float r = (float)((double)(wall_clock64() - t_begin) / ops);
+      __hip_atomic_store(a.rates + w, r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+  if (leader) {
+    a.flex_seg[w * 4 + 0] = pl;
+    a.flex_seg[w * 4 + 1] = pr;
+    a.flex_seg[w * 4 + 2] = ops;
+    a.flex_seg[w * 4 + 3] = 0;
+  }
+}
+
 __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) k_persistent(SolveArgs a) {
   __shared__ double red[kWG / kWave];
   __shared__ double s_E;
@@ -451,6 +580,10 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) k
     __syncthreads();
     G.local = s_task != 0;
     __syncthreads();
+  }
+  if (a.flex) {
+    flex_phase1(a, G, slot, part, par, red, &s_E, &s_flag, roll);
+    return;
   }
   for (;;) {
     if (threadIdx.x == 0) s_task = ld_relaxed(&G.task[tpar]);

@@ -16,8 +16,12 @@ def pytest_configure(config):
 def _ensure_library():
     lib = os.path.join(ROOT, "paper_2010_12478_amd", "libregscan.so")
     if not os.path.exists(lib):
-        from paper_2010_12478_amd.build import build
-        build()
+        import importlib.util   # build.py by path: the package needs the library to import
+        spec = importlib.util.spec_from_file_location(
+            "_regscan_build", os.path.join(ROOT, "paper_2010_12478_amd", "build.py"))
+        mod = importlib.util.module_from_spec(spec)
+        spec.loader.exec_module(mod)
+        mod.build()
 
 
 _ensure_library()

@@ -154,3 +154,45 @@ def test_scan_plans_agree_with_sequential_recursion_on_clean_series():
         dev = np.abs(tree.phi0 - seq.phi0)[:, :, mask]
         print(f"{algo}: max deviation from the sequential order {dev.max():.4f} px")
         assert dev.max() < 0.05
+
+
+# ------------------------------------------- flexible segments (Algorithm 1)
+
+def test_flex_orders_accepts_algorithm1_schedules_and_rejects_others():
+    from oracle.scan import flex_orders, flex_start
+    M, W = 9, 3
+    assert [flex_start(M, W, w) for w in range(W)] == [0, 4, 8]
+    # worker 0: 0 -> 1 -> 2; worker 1: 4 -> 5 (right first) -> 3; worker 2: 8 -> 7 -> 6
+    seg = [(0, 2), (3, 5), (6, 8)]
+    step = np.array([0, 1, 2, 2, 0, 1, 2, 1, 0])
+    orders = flex_orders(seg, step, M)
+    assert orders == [(0, [1, 2]), (4, [5, 3]), (8, [7, 6])]
+    bad = step.copy()
+    bad[3], bad[5] = 1, 2          # worker 1 stepped left first
+    with pytest.raises(ValueError):
+        flex_orders(seg, bad, M)
+    with pytest.raises(ValueError):
+        flex_orders([(0, 2), (4, 5), (6, 8)], step, M)    # element 3 uncovered
+    # worker 0 taking element 3 instead is legal too
+    assert flex_orders([(0, 3), (4, 5), (6, 8)], np.array([0, 1, 2, 3, 0, 1, 2, 1, 0]), M)[0] == (0, [1, 2, 3])
+    jump = np.array([0, 2, 1, 2, 0, 1, 2, 1, 0])           # worker 0 absorbs 2 before 1
+    with pytest.raises(ValueError):
+        flex_orders(seg, jump, M)
+
+
+def test_flex_scan_agrees_with_sequential_recursion_on_clean_series():
+    # any legal combination order lands on the same deformation as the
+    # sequential recursion up to the solver's accuracy (Section 2.3.3)
+    from oracle.scan import run_flex_scan
+    cfg = get_config(1, n_frames=10, noise=0.0, levels=1, max_iter=300, fixed_iter=False)
+    S = make_series(cfg.series)
+    fr = S.frames.numpy().astype(np.float64)
+    seq = run_scan(fr, cfg.solver, "seq")
+    seg = [(0, 2), (3, 5), (6, 8)]
+    step = np.array([0, 1, 2, 2, 0, 1, 2, 1, 0])
+    phi0, u_pair = run_flex_scan(fr, cfg.solver, seg, step, "lf")
+    assert np.array_equal(u_pair, seq.u_pair)
+    assert np.array_equal(phi0[:3], seq.phi0[:3])       # worker 0 is the sequential recursion
+    mask = _atom_mask(S, cfg.series, 0)
+    dev = np.abs(phi0 - seq.phi0)[:, :, mask]
+    assert dev.max() < 0.05
