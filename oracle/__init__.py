@@ -14,7 +14,9 @@ Modules
   autodiff      gradients of the warp + energy step w.r.t. both images and u
   mock          the scan on an artificial operator (microbenchmarks): operator
                 times, expected outputs, simulation of the execution forms
+  rigid         the rigid normalized-cross-correlation operator: energy,
+                gradient, multilevel flow, composition, its series scan
 """
-from . import autodiff, mock, plans, registration, scan
+from . import autodiff, mock, plans, registration, rigid, scan
 
-__all__ = ["autodiff", "mock", "plans", "registration", "scan"]
+__all__ = ["autodiff", "mock", "plans", "registration", "rigid", "scan"]

@@ -8,6 +8,9 @@ oxidation data, not available here).  Recipe, per frame k of a series:
   origin o ~ U[0, a)^2, amplitude 1 on a zero background;
 * frame    f_k(x) = L(x - d_k - w_k(x)) + n_k(x), n_k iid N(0, noise^2),
   plus N(0, extra_noise^2) on a seeded subset of frames;
+  (rigid series: f_k(y) = L(Phi_k^{-1}(y)) + n_k(y) with Phi_k a rotation
+  about the image centre and a translation whose parameters walk by
+  U[-RIGID_STEP_ALPHA, RIGID_STEP_ALPHA] and U[-delta, delta]^2 per frame)
 * drift    d_0 = 0, d_k = d_{k-1} + U[-delta, delta]^2 reflected into
   [-D, D], delta = min(a/4, D/2), so consecutive frames stay within half a
   lattice period of each other (Section 2.3.2) while the series as a whole
@@ -34,7 +37,7 @@ from dataclasses import dataclass
 import numpy as np
 import torch
 
-from .configs import SeriesSpec
+from .configs import RIGID_STEP_ALPHA, SeriesSpec
 
 
 @dataclass
@@ -136,3 +139,71 @@ def clean_frame(series: Series, k: int) -> np.ndarray:
     wx, wy = _distortion(spec, series.theta[k], xx, yy)
     return lattice_image(spec, series.origin, xx - series.drift[k, 0] - wx,
                          yy - series.drift[k, 1] - wy).numpy()
+
+
+def rigid_pair(spec: SeriesSpec, theta, seed_offset: int = 0):
+    """Reference R(x) = L(x) and template T(y) = L(phi^{-1}(y)) for the rigid
+    motion phi(x) = Rot(alpha)(x - c) + c + G, theta = (alpha, G_x, G_y),
+    c = ((w - 1) / 2, (h - 1) / 2), so that T(phi(x)) = R(x); iid noise of
+    spec.noise on both.  Returns float32 tensors [H][W]."""
+    origin, _, _, _ = _frame_params(spec)
+    H, W = spec.height, spec.width
+    yy, xx = torch.meshgrid(torch.arange(H, dtype=torch.float64), torch.arange(W, dtype=torch.float64), indexing="ij")
+    a, gx, gy = (float(v) for v in theta)
+    cx, cy = (W - 1) / 2.0, (H - 1) / 2.0
+    ux, uy = xx - cx - gx, yy - cy - gy
+    qx = math.cos(a) * ux + math.sin(a) * uy + cx
+    qy = -math.sin(a) * ux + math.cos(a) * uy + cy
+    R = lattice_image(spec, origin, xx, yy)
+    T = lattice_image(spec, origin, qx, qy)
+    if spec.noise > 0:
+        gen = torch.Generator()
+        gen.manual_seed(spec.seed + 7919 * (1 + seed_offset))
+        R = R + spec.noise * torch.randn((H, W), generator=gen, dtype=torch.float64)
+        T = T + spec.noise * torch.randn((H, W), generator=gen, dtype=torch.float64)
+    return R.to(torch.float32), T.to(torch.float32)
+
+
+@dataclass
+class RigidSeries:
+    spec: SeriesSpec
+    frames: torch.Tensor      # [N][H][W] float32
+    theta: np.ndarray         # [N][3] (alpha, G_x, G_y) of Phi_k; Phi_0 = identity
+
+
+def _rigid_frame(spec: SeriesSpec, origin, theta, xx, yy):
+    """L(Phi^{-1}(y)) for Phi(x) = Rot(alpha)(x - c) + c + G."""
+    a, gx, gy = (float(v) for v in theta)
+    cx, cy = (spec.width - 1) / 2.0, (spec.height - 1) / 2.0
+    ux, uy = xx - cx - gx, yy - cy - gy
+    qx = math.cos(a) * ux + math.sin(a) * uy + cx
+    qy = -math.sin(a) * ux + math.cos(a) * uy + cy
+    return lattice_image(spec, origin, qx, qy)
+
+
+def rigid_series(spec: SeriesSpec, device="cpu") -> RigidSeries:
+    """Lattice series under rigid motion: frame k is the lattice moved by
+    Phi_k, so f_k(Phi_k(x)) = f_0(x) up to noise and Phi_k is the motion that
+    registers frame k to frame 0.  Phi_0 = identity; the angle and the
+    translation of Phi_k walk from frame to frame (bounded steps, translation
+    reflected into [-D, D]^2)."""
+    origin, drift, _, _ = _frame_params(spec)
+    rng = np.random.Generator(np.random.PCG64(spec.seed + 104729))
+    n = spec.n_frames
+    theta = np.zeros((n, 3))
+    theta[:, 1:] = drift
+    for k in range(1, n):
+        theta[k, 0] = theta[k - 1, 0] + rng.uniform(-RIGID_STEP_ALPHA, RIGID_STEP_ALPHA)
+    dev = torch.device(device)
+    H, W = spec.height, spec.width
+    yy, xx = torch.meshgrid(torch.arange(H, dtype=torch.float64, device=dev),
+                            torch.arange(W, dtype=torch.float64, device=dev), indexing="ij")
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(spec.seed + 15485863)
+    frames = torch.empty((n, H, W), dtype=torch.float32, device=dev)
+    for k in range(n):
+        f = _rigid_frame(spec, origin, theta[k], xx, yy)
+        if spec.noise > 0:
+            f += spec.noise * torch.randn((H, W), generator=gen, dtype=torch.float64, device=dev)
+        frames[k] = f.to(torch.float32)
+    return RigidSeries(spec, frames, theta)
