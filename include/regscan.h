@@ -287,8 +287,45 @@ int scan_run_flex(const float* frames, int N, int H, int W, const reg_params_t* 
                   float* phi0, float* u_pair, int32_t* seg, int32_t* step, int64_t* counts, double* ms,
                   void* stream);
 
+/* Rigid registration with normalized cross-correlation, the paper's own
+ * operator (Definition "Image registration problem", Section 2.3.1):
+ *   phi(x) = Rot(alpha) (x - c) + c + G,  c = ((W - 1) / 2, (H - 1) / 2),
+ *   theta = (alpha [rad], G_x, G_y [px]),
+ *   E(theta) = 1 - NCC(R, T o phi), T sampled bilinearly with edge-clamped
+ *   taps (E = 1 with zero gradient when either image is constant);
+ * gradient flow theta <- theta - tau (dE/dalpha / r^2, dE/dG_x, dE/dG_y) with
+ * r^2 = ((W^2 - 1) + (H^2 - 1)) / 12 (the mean squared pixel distance from c),
+ * per level the stopping rule of reg_solve_batch, on the box pyramid: the
+ * initial guess enters the coarsest level with G / 2^(levels-1), each finer
+ * level starts from the coarser result with G doubled, alpha is unchanged.
+ * p->lambda is not used.
+ *   frames    [N][H][W]
+ *   ref_idx, tmpl_idx [B]  HOST int32 frame indices in [0, N)
+ *   theta0    [B][3] float64 initial guesses or NULL (identity)
+ *   theta     [B][3] float64 results (must not alias theta0)
+ *   iters     [B][levels] or NULL;  status [B] REG_S_* bits or NULL
+ * One persistent launch; the per-launch probe below records it. */
+int reg_rigid_solve_batch(const float* frames, int N, int H, int W,
+                          const int32_t* ref_idx, const int32_t* tmpl_idx,
+                          const double* theta0, double* theta, int32_t* iters, int32_t* status, int B,
+                          const reg_params_t* p, void* stream);
+
+/* The series registration of scan_run (Section 3) with the rigid operator:
+ * the pairwise registrations theta_{k-1,k} from the identity, then the plan's
+ * ops B(theta_ij, theta_jk) = reg_rigid(f_i, f_k) started from the
+ * composition phi_jk o phi_ij, whose parameters are
+ *   alpha = alpha_ij + alpha_jk,  G = Rot(alpha_jk) G_ij + G_jk.
+ *   phi0     [M][3] float64 out: theta_{0,k}, k = 1..M, M = N - 1
+ *   pairs    [M][3] float64 out: theta_{k-1,k}, or NULL (kept in workspace)
+ *   op_iters [M + n_ops][levels], status [M + n_ops]: as scan_run, or NULL
+ * One persistent launch for the pairwise phase and one per plan level. */
+int scan_run_rigid(const float* frames, int N, int H, int W, const reg_params_t* p,
+                   int algo, int chunk, int global_algo,
+                   double* phi0, double* pairs, int32_t* op_iters, int32_t* status, void* stream);
+
 /* Kernel-duration probe: total device time in milliseconds of the persistent
- * solve launches of the last scan_run / reg_solve_batch in REG_BATCHED mode
+ * solve launches of the last scan_run / reg_solve_batch in REG_BATCHED mode,
+ * reg_rigid_solve_batch or scan_run_rigid
  * (HIP events recorded around every launch on the launch stream), and the
  * number of launches.  HOST outputs; waits for those events. */
 int reg_last_solve_timing(double* total_ms, int* launches);

@@ -28,7 +28,7 @@ EXPORTS = (
     "reg_pyramid_energy_backward_f64", "reg_compose", "reg_restrict", "reg_prolong",
     "reg_solve_batch", "scan_plan", "scan_run", "reg_last_solve_timing", "reg_last_solve_launch_ms",
     "reg_set_tuning",
-    "reg_autotune", "reg_release", "scan_mock_run", "scan_run_flex",
+    "reg_autotune", "reg_release", "scan_mock_run", "scan_run_flex", "reg_rigid_solve_batch", "scan_run_rigid",
 )
 
 
@@ -91,6 +91,8 @@ _SIGS = {
     "reg_release": (None, []),
     "scan_mock_run": (_I, [_I, _I, _I, _I, _I, _I, _P, _P, _P, _P, _P, _P]),
     "scan_run_flex": (_I, [_P, _I, _I, _I, _P, _I, _I, _P, _P, _P, _P, _P, _P, _P]),
+    "reg_rigid_solve_batch": (_I, [_P, _I, _I, _I, _P, _P, _P, _P, _P, _P, _I, _P, _P]),
+    "scan_run_rigid": (_I, [_P, _I, _I, _I, _P, _I, _I, _I, _P, _P, _P, _P, _P]),
 }
 
 

@@ -238,6 +238,49 @@ def scan_run_flex(frames, params, workers, global_algo="lf", want_pairs=True):
     return phi0, u_pair, seg, step, list(counts), list(ms)
 
 
+def rigid_solve_batch(frames, ref_idx, tmpl_idx, params, theta0=None):
+    """Batch of multilevel rigid NCC registrations; returns (theta [B][3]
+    float64 (alpha, G_x, G_y), iters [B][L], status [B])."""
+    _need(frames, "frames")
+    N, H, W = frames.shape
+    ref = np.ascontiguousarray(np.asarray(ref_idx, dtype=np.int32))
+    tmp = np.ascontiguousarray(np.asarray(tmpl_idx, dtype=np.int32))
+    B = len(ref)
+    if len(tmp) != B:
+        raise ValueError("ref_idx and tmpl_idx differ in length")
+    dev = frames.device
+    if theta0 is not None:
+        _need(theta0, "theta0", torch.float64, (B, 3))
+    theta = torch.empty((B, 3), dtype=torch.float64, device=dev)
+    iters = torch.empty((B, params.levels), dtype=torch.int32, device=dev)
+    status = torch.empty(B, dtype=torch.int32, device=dev)
+    p = params_struct(params)
+    check(lib.reg_rigid_solve_batch(_ptr(frames), N, H, W, ref.ctypes.data_as(ctypes.c_void_p),
+                                    tmp.ctypes.data_as(ctypes.c_void_p), _ptr(theta0), _ptr(theta), _ptr(iters),
+                                    _ptr(status), B, ctypes.byref(p), _stream()))
+    return theta, iters, status
+
+
+def scan_run_rigid(frames, params, algo="seq", chunk=0, global_algo="lf", want_pairs=True):
+    """Series registration with the rigid NCC operator.  Returns (phi0 [M][3],
+    pairs [M][3] or None, op_iters [M + n_ops][L], status [M + n_ops])."""
+    _need(frames, "frames")
+    N, H, W = frames.shape
+    M = N - 1
+    from ._lib import plan as _plan
+    n_ops = len(_plan(M, algo, chunk, global_algo)[0])
+    dev = frames.device
+    phi0 = torch.empty((M, 3), dtype=torch.float64, device=dev)
+    pairs = torch.empty((M, 3), dtype=torch.float64, device=dev) if want_pairs else None
+    iters = torch.empty((M + n_ops, params.levels), dtype=torch.int32, device=dev)
+    status = torch.empty(M + n_ops, dtype=torch.int32, device=dev)
+    p = params_struct(params)
+    check(lib.scan_run_rigid(_ptr(frames), N, H, W, ctypes.byref(p), SCAN_ALGOS[algo], int(chunk),
+                             SCAN_ALGOS[global_algo], _ptr(phi0), _ptr(pairs), _ptr(iters), _ptr(status),
+                             _stream()))
+    return phi0, pairs, iters, status
+
+
 def last_solve_timing():
     """(total ms, launches) of the persistent launches of the last batched call."""
     ms, n = ctypes.c_double(0), ctypes.c_int(0)

@@ -64,6 +64,8 @@ struct State {
   unsigned spin_limit = 1u << 22;   // ~seconds of polling before the watchdog aborts a run
   DevBuf pyr, slots, part, ctrl, tasks, nodes, upair, iters, status, misc, lvl, flow, mock;
   DevBuf flexw, flexn, flext, flexf;   // flexible-segment scan: worker state, pool, tasks, flow
+  DevBuf rnodes, rtasks, rpart, rctrl;   // rigid operator: parameters, descriptors, sums, queue
+  int rigid_blocks_per_cu = 0;
   double* h_E = nullptr;   // pinned host scalar for the plain path
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
   size_t events_used = 0;
@@ -1387,6 +1389,185 @@ int scan_run_flex(const float* frames, int N, int H, int W, const reg_params_t* 
   }
   return REG_OK;
 }
+
+}  // extern "C"
+
+// ------------------------------------------------------------ rigid operator
+
+namespace {
+
+// Runs n rigid registrations (device descriptors) with one persistent launch:
+// groups of g workgroups on one XCD, g the largest power of two <= 16 that
+// keeps a group per task (rounded up to 8) resident.
+int run_rigid(RigidArgs a, const RigidTask* d_tasks, int n, hipStream_t s) {
+  if (n == 0) return REG_OK;
+  if (!g.rigid_blocks_per_cu) {
+    int nb = 0;
+    HIPCHK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, rigid_kernel(), kWG, 0));
+    if (nb < 1) return fail(REG_E_HIP, "rigid kernel cannot be resident");
+    g.rigid_blocks_per_cu = nb;
+  }
+  const int slots = g.rigid_blocks_per_cu * g.n_cu;
+  const int want = (n + 7) / 8 * 8;
+  int gs = 1;
+  while (gs * 2 <= 16 && (long long)want * gs * 2 <= slots) gs *= 2;
+  int groups = std::min(want, std::max(8, slots / gs / 8 * 8));
+  const int ctrl_ints = kCtrlHead + kCtrlGroup * groups;
+  TRY(ensure(g.rctrl, (size_t)ctrl_ints * sizeof(int)));
+  TRY(ensure(g.rpart, (size_t)groups * 2 * gs * 16 * sizeof(double)));
+  a.tasks = d_tasks;
+  a.n_tasks = n;
+  a.g = gs;
+  a.ctrl = (int*)g.rctrl.p;
+  a.part = (double*)g.rpart.p;
+  a.spin_limit = g.spin_limit;
+  HIPCHK(launch_reset_rigid(a.ctrl, ctrl_ints, d_tasks, n, s));
+  hipEvent_t* ev = next_events();
+  if (ev) HIPCHK(hipEventRecord(ev[0], s));
+  HIPCHK(launch_rigid(a, groups * gs, s));
+  if (ev) HIPCHK(hipEventRecord(ev[1], s));
+  return REG_OK;
+}
+
+RigidArgs rigid_args(const Pyr& P, int H, int W, const reg_params_t* p) {
+  RigidArgs a;
+  std::memset(&a, 0, sizeof a);
+  for (int l = 0; l < p->levels; ++l) {
+    a.pyr[l] = P.lv[l];
+    a.fstride[l] = P.fstride[l];
+    a.pitch[l] = P.pitch[l];
+  }
+  a.H = H;
+  a.W = W;
+  a.levels = p->levels;
+  a.max_iter = p->max_iter;
+  a.fixed_iter = p->fixed_iter ? 1 : 0;
+  a.tau = p->tau;
+  a.rel_tol = p->rel_tol;
+  return a;
+}
+
+int upload_rigid(const std::vector<RigidTask>& t, hipStream_t s) {
+  TRY(ensure(g.rtasks, t.size() * sizeof(RigidTask)));
+  HIPCHK(hipMemcpyAsync(g.rtasks.p, t.data(), t.size() * sizeof(RigidTask), hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));   // the host vector may go out of scope
+  return REG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int reg_rigid_solve_batch(const float* frames, int N, int H, int W, const int32_t* ref_idx, const int32_t* tmpl_idx,
+                          const double* theta0, double* theta, int32_t* iters, int32_t* status, int B,
+                          const reg_params_t* p, void* stream) {
+  std::lock_guard<std::recursive_mutex> lk(g_mu);
+  TRY(check_dims(B, H, W));
+  TRY(check_params(p, H, W));
+  if (N < 1) return fail(REG_E_INVALID, "N = %d frames", N);
+  if (B == 0) return REG_OK;
+  if (!frames || !ref_idx || !tmpl_idx || !theta) return fail(REG_E_INVALID, "NULL pointer");
+  if (theta0 && theta0 == theta) return fail(REG_E_INVALID, "theta aliases theta0");
+  for (int b = 0; b < B; ++b)
+    if (ref_idx[b] < 0 || ref_idx[b] >= N || tmpl_idx[b] < 0 || tmpl_idx[b] >= N)
+      return fail(REG_E_INVALID, "frame index out of range at item %d", b);
+  TRY(ensure_device());
+  hipStream_t s = (hipStream_t)stream;
+  Pyr P;
+  TRY(build_pyramid(frames, N, H, W, p->levels, P, s));
+  std::vector<RigidTask> tasks(B);
+  for (int b = 0; b < B; ++b) {
+    RigidTask& d = tasks[b];
+    d.ref = ref_idx[b];
+    d.tmpl = tmpl_idx[b];
+    d.kind = theta0 ? 2 : 0;
+    d.pad = 0;
+    d.ta = theta0 ? theta0 + 3 * b : nullptr;
+    d.tb = nullptr;
+    d.out = theta + 3 * b;
+    d.iters = iters ? iters + (size_t)b * p->levels : nullptr;
+    d.status = status ? status + b : nullptr;
+  }
+  TRY(upload_rigid(tasks, s));
+  g.events_used = 0;
+  return run_rigid(rigid_args(P, H, W, p), (const RigidTask*)g.rtasks.p, B, s);
+}
+
+int scan_run_rigid(const float* frames, int N, int H, int W, const reg_params_t* p, int algo, int chunk,
+                   int global_algo, double* phi0, double* pairs, int32_t* op_iters, int32_t* status, void* stream) {
+  std::lock_guard<std::recursive_mutex> lk(g_mu);
+  TRY(check_dims(1, H, W));
+  TRY(check_params(p, H, W));
+  if (N < 2) return fail(REG_E_INVALID, "a series needs N >= 2 frames (got %d)", N);
+  if (!frames || !phi0) return fail(REG_E_INVALID, "NULL pointer");
+  if (algo < SCAN_SEQ || algo > SCAN_HIER) return fail(REG_E_INVALID, "unknown scan algorithm %d", algo);
+  if (algo == SCAN_HIER && (global_algo < SCAN_SEQ || global_algo > SCAN_BRENT_KUNG))
+    return fail(REG_E_INVALID, "unknown global algorithm %d", global_algo);
+  const int M = N - 1;
+  std::vector<PlanOp> plan;
+  int n_levels = 0;
+  try {
+    if (rs::build_plan(M, algo, chunk, global_algo, plan, n_levels) != 0)
+      return fail(REG_E_INVALID, "invalid plan arguments");
+  } catch (const std::exception& e) {
+    return fail(REG_E_INVALID, "plan construction failed: %s", e.what());
+  }
+  TRY(ensure_device());
+  hipStream_t s = (hipStream_t)stream;
+  const int L = p->levels;
+  const size_t n_ops = plan.size();
+  // node parameters: elements in `pairs` (or workspace), every op output in
+  // workspace, except that an op yielding a prefix (0, k) writes phi0[k - 1]
+  const std::vector<int> fin = final_nodes(plan, M);
+  for (int k = 1; k < M; ++k)
+    if (fin[k] < M) return fail(REG_E_INVALID, "plan yields no prefix (0, %d)", k + 1);
+  TRY(ensure(g.rnodes, (size_t)(M + n_ops) * 3 * sizeof(double)));
+  double* ws = (double*)g.rnodes.p;
+  std::vector<double*> node(M + n_ops);
+  for (int m = 0; m < M; ++m) node[m] = (pairs ? pairs : ws) + 3 * m;
+  for (size_t q = 0; q < n_ops; ++q) node[M + q] = ws + 3 * (M + q);
+  for (int k = 1; k < M; ++k) node[fin[k]] = phi0 + 3 * k;
+  Pyr P;
+  TRY(build_pyramid(frames, N, H, W, L, P, s));
+  std::vector<RigidTask> tasks(M + n_ops);
+  std::vector<int> level_of(M + n_ops, 0);
+  for (int m = 0; m < M; ++m) {
+    RigidTask& d = tasks[m];
+    d = RigidTask{m, m + 1, 0, 0, nullptr, nullptr, node[m], nullptr, nullptr};
+  }
+  for (size_t q = 0; q < n_ops; ++q) {
+    const PlanOp& o = plan[q];
+    RigidTask& d = tasks[M + q];
+    d = RigidTask{o.i, o.k, 1, 0, node[o.a], node[o.b], node[o.out], nullptr, nullptr};
+    level_of[M + q] = o.level;
+  }
+  for (size_t t = 0; t < tasks.size(); ++t) {
+    tasks[t].iters = op_iters ? op_iters + t * L : nullptr;
+    tasks[t].status = status ? status + t : nullptr;
+  }
+  // device descriptors grouped by level (stable), one launch per level
+  std::vector<int> order(tasks.size());
+  for (size_t t = 0; t < order.size(); ++t) order[t] = (int)t;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return level_of[x] < level_of[y]; });
+  std::vector<RigidTask> sorted(tasks.size());
+  for (size_t t = 0; t < order.size(); ++t) sorted[t] = tasks[order[t]];
+  TRY(upload_rigid(sorted, s));
+  const RigidArgs a = rigid_args(P, H, W, p);
+  g.events_used = 0;
+  size_t first = 0;
+  while (first < sorted.size()) {
+    size_t last = first;
+    while (last < sorted.size() && level_of[order[last]] == level_of[order[first]]) ++last;
+    TRY(run_rigid(a, (const RigidTask*)g.rtasks.p + first, (int)(last - first), s));
+    first = last;
+  }
+  HIPCHK(hipMemcpyAsync(phi0, node[0], 3 * sizeof(double), hipMemcpyDeviceToDevice, s));
+  return REG_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
 
 int scan_mock_run(int M, int algo, int chunk, int global_algo, int mode, int workers, const mock_params_t* p,
                   int32_t* prefix, int32_t* seg_out, int64_t* counts, double* ms, void* stream) {

@@ -78,6 +78,35 @@ struct SolveArgs {
 
 size_t slot_floats_for(int H, int W, int levels, size_t* lvl_off, size_t* bufB_off);
 
+// Rigid registration with normalized cross-correlation (solver.hip).
+struct RigidTask {
+  int32_t ref, tmpl;     // frame indices
+  int32_t kind;          // 0 identity, 1 composition of ta and tb, 2 given ta
+  int32_t pad;
+  const double* ta;      // theta_ij or theta0: (alpha, G_x, G_y)
+  const double* tb;      // theta_jk
+  double* out;           // [3]
+  int32_t* iters;        // [levels] or nullptr
+  int32_t* status;       // [1] or nullptr
+};
+constexpr int kRigidSums = 14;   // sum a, b, aa, bb, ab; per parameter sum g, a g, b g
+struct RigidArgs {
+  const float* pyr[kMaxLevelsHost];   // padded pyramid (see SolveArgs)
+  size_t fstride[kMaxLevelsHost];
+  int pitch[kMaxLevelsHost];
+  int H, W, levels, max_iter, fixed_iter;
+  double tau, rel_tol;
+  const RigidTask* tasks;
+  int n_tasks;
+  int g;                 // workgroups per registration
+  int* ctrl;             // [0] ticket, [1] abort, per group at kCtrlHead + kCtrlGroup * id
+  double* part;          // [groups][2][g][16]: per-member partial sums, by iteration parity
+  unsigned spin_limit;
+};
+const void* rigid_kernel();
+hipError_t launch_rigid(const RigidArgs& a, int grid, hipStream_t s);
+hipError_t launch_reset_rigid(int* ctrl, int n_ints, const RigidTask* tasks, int n_tasks, hipStream_t s);
+
 // Mock-operator scan (mock.hip).  A node is the frame range (i, k) as int2.
 struct MockOp {
   int out, a, b, pad;   // node ids: out = a (.) b

@@ -446,98 +446,81 @@ __device__ __forceinline__ int flex_gap_size(const unsigned long long* gaps, int
   return (int)(g >> 32) - (int)(g & 0xffffffffu) + 1;
 }
 
-__device__ void flex_phase1(const SolveArgs& a, Group& G, float* slot, double* part, int& par, double* red,
-                            double* s_E, int* s_flag, float2* roll) {
+// State a flexible-segment worker's leader keeps between registrations.
+struct FlexState {
+  int pl, pr, ops;
+  unsigned long long t0;
+};
+
+// The next registration of worker w = G.id (see flex_claim): the leader picks
+// the direction, claims the element and publishes the descriptor and a
+// command word; after the group barrier every thread reads them back.
+// Returns 1 with *d filled, 0 when the worker's gaps are empty, -1 on abort.
+__device__ int flex_next(const SolveArgs& a, Group& G, FlexState& F, TaskDesc& d, int* s_flag,
+                         unsigned long long* s_desc) {
   int* abort_flag = a.ctrl + 1;
   const int w = G.id, P = a.flex_workers;
-  if (w >= P) return;   // groups are launched in multiples of 8: the surplus has no segment
   const size_t nf = (size_t)2 * a.H * a.W;
-  const int L = a.levels;
   unsigned long long* desc = a.flex_desc + (size_t)w * 8;
-  // leader state
-  int pl = a.starts[w], pr = a.starts[w], ops = 0;
-  unsigned long long t_begin = 0;
-  const bool leader = G.member == 0 && threadIdx.x == 0;
-  if (leader) t_begin = wall_clock64();
-  for (;;) {
-    if (leader) {
-      int e = -1;
-      bool right = true;
-      for (;;) {
-        const int sL = w > 0 ? flex_gap_size(a.gaps, w - 1) : 0;
-        const int sR = w < P - 1 ? flex_gap_size(a.gaps, w) : 0;
-        if (sL <= 0 && sR <= 0) break;
-        if (ops == 0 && sR > 0) right = true;
-        else if (sL > 0 && sR > 0)
-          right = !(__hip_atomic_load(a.rates + w - 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >
-                    __hip_atomic_load(a.rates + w + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-        else right = sL <= 0;
-        e = right ? flex_claim(a.gaps, w, true) : flex_claim(a.gaps, w - 1, false);
-        if (e >= 0) break;
-      }
-      int cmd = 0;
-      if (e >= 0) {
-        cmd = 1;
-        const float* res = ops == 0 ? a.elem + (size_t)a.starts[w] * nf
-                           : w == 0 ? a.phi0 + (size_t)pr * nf
-                                    : a.flex_buf + ((size_t)w * 2 + ((ops - 1) & 1)) * nf;
-        float* next = a.flex_buf + ((size_t)w * 2 + (ops & 1)) * nf;
-        TaskDesc d;
-        d.kind = 1;
-        d.pad = 0;
-        if (right) {
-          d.ref = pl;
-          d.tmpl = e + 1;
-          d.ua = res;
-          d.ub = a.elem + (size_t)e * nf;
-          d.out = w == 0 ? a.phi0 + (size_t)e * nf : next;
-        } else {
-          d.ref = e;
-          d.tmpl = pr + 1;
-          d.ua = a.elem + (size_t)e * nf;
-          d.ub = res;
-          d.out = next;
-        }
-        d.iters = a.elem_iters + (size_t)e * L;
-        d.status = a.elem_status + e;
-        unsigned long long words[7];
-        __builtin_memcpy(words, &d, sizeof d);
-        for (int q = 0; q < 7; ++q)
-          __hip_atomic_store(desc + q, words[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        a.elem_step[e] = ops + 1;
-        if (right) pr = e;
-        else pl = e;
-      }
-      __hip_atomic_store(G.task, cmd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (G.member == 0 && threadIdx.x == 0) {
+    int e = -1;
+    bool right = true;
+    for (;;) {
+      const int sL = w > 0 ? flex_gap_size(a.gaps, w - 1) : 0;
+      const int sR = w < P - 1 ? flex_gap_size(a.gaps, w) : 0;
+      if (sL <= 0 && sR <= 0) break;
+      if (F.ops == 0 && sR > 0) right = true;
+      else if (sL > 0 && sR > 0)
+        right = !(__hip_atomic_load(a.rates + w - 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >
+                  __hip_atomic_load(a.rates + w + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+      else right = sL <= 0;
+      e = right ? flex_claim(a.gaps, w, true) : flex_claim(a.gaps, w - 1, false);
+      if (e >= 0) break;
     }
-    if (!group_sync(G, abort_flag, a.spin_limit, s_flag)) return;
-    __shared__ int s_cmd;
-    __shared__ unsigned long long s_desc[7];
-    if (threadIdx.x == 0) s_cmd = __hip_atomic_load(G.task, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (threadIdx.x < 7) s_desc[threadIdx.x] = __hip_atomic_load(desc + threadIdx.x, __ATOMIC_RELAXED,
-                                                                 __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
-    if (!s_cmd) break;
-    TaskDesc d;
-    __builtin_memcpy(&d, s_desc, sizeof d);
-    __syncthreads();
-    // the running result was written by this group's previous registration
-    // through other CUs' L1s: drop stale lines before reading it
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    if (!run_task(a, d, G, slot, part, par, red, s_E, s_flag, roll)) return;
-    if (!group_sync(G, abort_flag, a.spin_limit, s_flag)) return;
-    if (leader) {
-      ++ops;
-      const float r = (float)((double)(wall_clock64() - t_begin) / ops);
-      __hip_atomic_store(a.rates + w, r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    unsigned long long cmd = 0;
+    if (e >= 0) {
+      cmd = 1;
+      const float* res = F.ops == 0 ? a.elem + (size_t)a.starts[w] * nf
+                         : w == 0   ? a.phi0 + (size_t)F.pr * nf
+                                    : a.flex_buf + ((size_t)w * 2 + ((F.ops - 1) & 1)) * nf;
+      const float* el = a.elem + (size_t)e * nf;
+      float* out = w == 0 ? a.phi0 + (size_t)e * nf : a.flex_buf + ((size_t)w * 2 + (F.ops & 1)) * nf;
+      const int ref = right ? F.pl : e, tmpl = right ? e + 1 : F.pr + 1;
+      const unsigned long long words[7] = {
+          (unsigned long long)(unsigned)ref | ((unsigned long long)(unsigned)tmpl << 32),
+          1ull,   // kind 1: composition of ua and ub
+          (unsigned long long)(right ? res : el),
+          (unsigned long long)(right ? el : res),
+          (unsigned long long)out,
+          (unsigned long long)(a.elem_iters + (size_t)e * a.levels),
+          (unsigned long long)(a.elem_status + e)};
+#pragma unroll
+      for (int q = 0; q < 7; ++q) __hip_atomic_store(desc + q, words[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      a.elem_step[e] = F.ops + 1;
+      if (right) F.pr = e;
+      else F.pl = e;
     }
+    __hip_atomic_store(desc + 7, cmd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
-  if (leader) {
-    a.flex_seg[w * 4 + 0] = pl;
-    a.flex_seg[w * 4 + 1] = pr;
-    a.flex_seg[w * 4 + 2] = ops;
-    a.flex_seg[w * 4 + 3] = 0;
-  }
+  if (!group_sync(G, abort_flag, a.spin_limit, s_flag)) return -1;
+  if (threadIdx.x < 8) s_desc[threadIdx.x] = __hip_atomic_load(desc + threadIdx.x, __ATOMIC_RELAXED,
+                                                               __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  if (s_desc[7] == 0) return 0;
+  d.ref = (int)(s_desc[0] & 0xffffffffu);
+  d.tmpl = (int)(s_desc[0] >> 32);
+  d.kind = 1;
+  d.pad = 0;
+  d.ua = (const float*)s_desc[2];
+  d.ub = (const float*)s_desc[3];
+  d.out = (float*)s_desc[4];
+  d.iters = (int32_t*)s_desc[5];
+  d.status = (int32_t*)s_desc[6];
+  __syncthreads();
+  // the running result was written by this group's previous registration
+  // through other CUs' L1s: drop stale lines before reading it
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return 1;
 }
 
 __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) k_persistent(SolveArgs a) {
@@ -581,19 +564,40 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) k
     G.local = s_task != 0;
     __syncthreads();
   }
+  FlexState F{0, 0, 0, 0};
+  __shared__ unsigned long long s_desc[8];
   if (a.flex) {
-    flex_phase1(a, G, slot, part, par, red, &s_E, &s_flag, roll);
-    return;
+    if (G.id >= a.flex_workers) return;   // groups come in multiples of 8: the surplus has no segment
+    F.pl = F.pr = a.starts[G.id];
+    if (G.member == 0 && threadIdx.x == 0) F.t0 = wall_clock64();
   }
   for (;;) {
-    if (threadIdx.x == 0) s_task = ld_relaxed(&G.task[tpar]);
-    __syncthreads();
-    const int t = s_task;
-    if (t >= a.n_tasks) break;
-    // dataflow: the inputs were written by other groups, possibly on other
-    // XCDs, and published with an agent-scope release
-    if (a.dataflow) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    if (!run_task(a, a.tasks[t], G, slot, part, par, red, &s_E, &s_flag, roll)) return;
+    TaskDesc d;
+    int t = 0;
+    if (a.flex) {
+      const int r = flex_next(a, G, F, d, &s_flag, s_desc);
+      if (r < 0) return;
+      if (r == 0) break;
+    } else {
+      if (threadIdx.x == 0) s_task = ld_relaxed(&G.task[tpar]);
+      __syncthreads();
+      t = s_task;
+      if (t >= a.n_tasks) break;
+      // dataflow: the inputs were written by other groups, possibly on other
+      // XCDs, and published with an agent-scope release
+      if (a.dataflow) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      d = a.tasks[t];
+    }
+    if (!run_task(a, d, G, slot, part, par, red, &s_E, &s_flag, roll)) return;
+    if (a.flex) {
+      if (!group_sync(G, abort_flag, a.spin_limit, &s_flag)) return;
+      if (G.member == 0 && threadIdx.x == 0) {
+        ++F.ops;
+        const float r = (float)((double)(wall_clock64() - F.t0) / F.ops);
+        __hip_atomic_store(a.rates + G.id, r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      continue;
+    }
     tpar ^= 1;
     if (a.dataflow) {
       // publish this task's output device-wide, then (leader) release its
@@ -615,11 +619,217 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) k
                          __HIP_MEMORY_SCOPE_AGENT);
     if (!group_sync(G, abort_flag, a.spin_limit, &s_flag)) return;
   }
+  if (a.flex && G.member == 0 && threadIdx.x == 0) {
+    a.flex_seg[G.id * 4 + 0] = F.pl;
+    a.flex_seg[G.id * 4 + 1] = F.pr;
+    a.flex_seg[G.id * 4 + 2] = F.ops;
+    a.flex_seg[G.id * 4 + 3] = 0;
+  }
+}
+
+// ------------------------------------------------------- rigid operator
+
+// theta of phi_jk o phi_ij about the common centre: angles add,
+// G = Rot(alpha_jk) G_ij + G_jk.
+__device__ __forceinline__ void rigid_compose(const double* t1, const double* t2, double* out) {
+#pragma clang fp contract(off)
+  const double c = cos(t2[0]), s = sin(t2[0]);
+  out[0] = t1[0] + t2[0];
+  out[1] = c * t1[1] - s * t1[2] + t2[1];
+  out[2] = s * t1[1] + c * t1[2] + t2[2];
+}
+
+// Rigid registration with normalized cross-correlation (the paper's operator,
+// Definition "Image registration problem", Section 2.3.1): phi(x) =
+// Rot(alpha)(x - c) + c + G about the image centre c, E = 1 - NCC(R, T o phi),
+// gradient flow in the metric diag(r^2, 1, 1) (r^2: mean squared pixel
+// distance from c) on the padded pyramid, G halved per coarser level.  A
+// group of g workgroups takes registrations from the ticket queue; per
+// iteration every member streams its rows once, accumulating in double the 14
+// sums that give NCC and its gradient (sum a, b, a^2, b^2, ab and per
+// parameter sum g_p, a g_p, b g_p, with g_p = grad T(phi(x)) . dphi/dtheta_p),
+// publishes them, and after the group barrier every thread adds the members'
+// sums in member order and takes the same step.
+__global__ void __launch_bounds__(kWG) k_rigid(RigidArgs a) {
+  __shared__ double red[kWG / kWave][16];
+  __shared__ double s_sum[16];
+  __shared__ int s_flag, s_task;
+  const int xcd = blockIdx.x & 7, lb = blockIdx.x >> 3;
+  Group G;
+  G.g = a.g;
+  G.member = lb % a.g;
+  G.id = (lb / a.g) * 8 + xcd;
+  int* gctl = a.ctrl + kCtrlHead + kCtrlGroup * G.id;
+  G.arrive = gctl;
+  G.task = gctl + kMaxGroup;
+  G.xcc = gctl + 2 * kMaxGroup;
+  G.epoch = 0;
+  G.local = false;
+  int* abort_flag = a.ctrl + 1;
+  double* part = a.part + (size_t)G.id * 2 * a.g * 16;
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
+  int tpar = 0, par = 0;
+  if (G.member == 0 && threadIdx.x == 0)
+    __hip_atomic_store(&G.task[0], atomicAdd(a.ctrl, 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (!group_sync(G, abort_flag, a.spin_limit, &s_flag)) return;
+  for (;;) {
+    if (threadIdx.x == 0) s_task = ld_relaxed(&G.task[tpar]);
+    __syncthreads();
+    const int t = s_task;
+    if (t >= a.n_tasks) break;
+    const RigidTask d = a.tasks[t];
+    double th[3] = {0.0, 0.0, 0.0};
+    if (d.kind == 1) rigid_compose(d.ta, d.tb, th);
+    else if (d.kind == 2) th[0] = d.ta[0], th[1] = d.ta[1], th[2] = d.ta[2];
+    const double down = (double)(1 << (a.levels - 1));
+    th[1] = th[1] / down;
+    th[2] = th[2] / down;
+    int iters[kMaxLevels];
+    int status = 0;
+    bool dead = false;
+    for (int l = a.levels - 1; l >= 0; --l) {
+      iters[l] = 0;
+      if (dead) continue;
+      if (l < a.levels - 1) {
+        th[1] = 2.0 * th[1];
+        th[2] = 2.0 * th[2];
+      }
+      const int h = a.H >> l, w = a.W >> l, pitch = a.pitch[l];
+      const float* Rp = a.pyr[l] + (size_t)d.ref * a.fstride[l];
+      const float* Tp = a.pyr[l] + (size_t)d.tmpl * a.fstride[l];
+      const ReadBuf rb(Rp), tb(Tp - pitch - 1);   // T from its border element (-1, -1)
+      const double r2 = ((double)w * w - 1.0 + ((double)h * h - 1.0)) / 12.0;
+      const double cx = (w - 1) / 2.0, cy = (h - 1) / 2.0;
+      const double n = (double)h * w;
+      const int row0 = (int)((long long)G.member * h / a.g), row1 = (int)((long long)(G.member + 1) * h / a.g);
+      const int p_end = (row1 - row0) * w;
+      double e_prev = 0.0;
+      int it = 0;
+      for (; it < a.max_iter; ++it) {
+        double acc[kRigidSums];
+#pragma unroll
+        for (int j = 0; j < kRigidSums; ++j) acc[j] = 0.0;
+        {
+#pragma clang fp contract(off)
+          const double ca = cos(th[0]), sa = sin(th[0]);
+          int x = threadIdx.x % w, y = row0 + threadIdx.x / w;
+          for (int q = threadIdx.x; q < p_end; q += kWG) {
+            const double dx = x - cx, dy = y - cy;
+            const double px = ca * dx - sa * dy + cx + th[1];
+            const double py = sa * dx + ca * dy + cy + th[2];
+            const double fx0 = floor(px), fy0 = floor(py);
+            const double fx = px - fx0, fy = py - fy0;
+            // the cell clamped to [-1, w-1] x [-1, h-1], offset by the border
+            const int cxi = (int)fmin(fmax(fx0, -1.0), (double)(w - 1)) + 1;
+            const int cyi = (int)fmin(fmax(fy0, -1.0), (double)(h - 1)) + 1;
+            const int o = __mul24(cyi, pitch) + cxi;
+            const double i00 = tb.f32(o, 0), i01 = tb.f32(o, 1);
+            const double i10 = tb.f32(o, pitch), i11 = tb.f32(o, pitch + 1);
+            const double av = rb.f32(__mul24(y, pitch) + x);
+            const double ox = 1.0 - fx, oy = 1.0 - fy;
+            const double b = oy * (ox * i00 + fx * i01) + fy * (ox * i10 + fx * i11);
+            const double bx = oy * (i01 - i00) + fy * (i11 - i10);
+            const double by = ox * (i10 - i00) + fx * (i11 - i01);
+            const double ga = bx * (-sa * dx - ca * dy) + by * (ca * dx - sa * dy);
+            acc[0] += av;
+            acc[1] += b;
+            acc[2] = fma(av, av, acc[2]);
+            acc[3] = fma(b, b, acc[3]);
+            acc[4] = fma(av, b, acc[4]);
+            acc[5] += ga;
+            acc[6] += bx;
+            acc[7] += by;
+            acc[8] = fma(av, ga, acc[8]);
+            acc[9] = fma(av, bx, acc[9]);
+            acc[10] = fma(av, by, acc[10]);
+            acc[11] = fma(b, ga, acc[11]);
+            acc[12] = fma(b, bx, acc[12]);
+            acc[13] = fma(b, by, acc[13]);
+            x += kWG;
+            while (x >= w) {
+              x -= w;
+              ++y;
+            }
+          }
+        }
+        // member partial sums: butterfly per wavefront, then the 4 wavefronts
+#pragma unroll
+        for (int j = 0; j < kRigidSums; ++j) {
+          const double v = wave_sum(acc[j]);
+          if (lane == 0) red[wave][j] = v;
+        }
+        __syncthreads();
+        double* pp = part + (size_t)par * a.g * 16;
+        if (threadIdx.x < kRigidSums)
+          pp[G.member * 16 + threadIdx.x] =
+              ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
+        if (!group_sync(G, abort_flag, a.spin_limit, &s_flag)) return;
+        if (threadIdx.x < kRigidSums) {
+          const SharedBuf pb(pp);
+          double v = 0.0;
+          for (int m = 0; m < a.g; ++m) v += pb.f64(m * 16 + threadIdx.x);
+          s_sum[threadIdx.x] = v;
+        }
+        __syncthreads();
+        par ^= 1;
+        double E, g0, g1, g2;
+        {
+#pragma clang fp contract(off)
+          const double abar = s_sum[0] / n, bbar = s_sum[1] / n;
+          const double saa = s_sum[2] - n * abar * abar, sbb = s_sum[3] - n * bbar * bbar;
+          const double sab = s_sum[4] - n * abar * bbar;
+          if (!(saa * sbb > 0.0)) {
+            E = 1.0;
+            g0 = g1 = g2 = 0.0;
+          } else {
+            const double den = sqrt(saa * sbb), ncc = sab / den;
+            E = 1.0 - ncc;
+            g0 = -((s_sum[8] - abar * s_sum[5]) / den - ncc * (s_sum[11] - bbar * s_sum[5]) / sbb);
+            g1 = -((s_sum[9] - abar * s_sum[6]) / den - ncc * (s_sum[12] - bbar * s_sum[6]) / sbb);
+            g2 = -((s_sum[10] - abar * s_sum[7]) / den - ncc * (s_sum[13] - bbar * s_sum[7]) / sbb);
+          }
+        }
+        if (!isfinite(E)) {
+          status |= 2;   // REG_S_NONFINITE
+          dead = true;
+          break;
+        }
+        if (!a.fixed_iter && it > 0 && level_stops(e_prev, E, a.rel_tol)) break;
+        e_prev = E;
+        {
+#pragma clang fp contract(off)
+          th[0] = th[0] - a.tau * g0 / r2;
+          th[1] = th[1] - a.tau * g1;
+          th[2] = th[2] - a.tau * g2;
+        }
+      }
+      iters[l] = it;
+      if (it == a.max_iter && !a.fixed_iter) status |= 1;   // REG_S_MAXITER
+    }
+    if (G.member == 0 && threadIdx.x == 0) {
+      const double nan = __builtin_nan("");
+      d.out[0] = dead ? nan : th[0];
+      d.out[1] = dead ? nan : th[1];
+      d.out[2] = dead ? nan : th[2];
+      if (d.iters)
+        for (int l = 0; l < a.levels; ++l) d.iters[l] = iters[l];
+      if (d.status) *d.status = status;
+      __hip_atomic_store(&G.task[tpar ^ 1], atomicAdd(a.ctrl, 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    tpar ^= 1;
+    if (!group_sync(G, abort_flag, a.spin_limit, &s_flag)) return;
+  }
 }
 
 // Clears the queue / barrier words and marks every task aborted until it
 // completes (a task the watchdog never let finish keeps that status).
 __global__ void k_reset(int* ctrl, int n_ints, const TaskDesc* tasks, int n_tasks) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_ints; i += gridDim.x * blockDim.x) ctrl[i] = 0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_tasks; i += gridDim.x * blockDim.x)
+    if (tasks[i].status) *tasks[i].status = 4;   // REG_S_ABORTED
+}
+
+__global__ void k_reset_rigid(int* ctrl, int n_ints, const RigidTask* tasks, int n_tasks) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_ints; i += gridDim.x * blockDim.x) ctrl[i] = 0;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_tasks; i += gridDim.x * blockDim.x)
     if (tasks[i].status) *tasks[i].status = 4;   // REG_S_ABORTED
@@ -692,6 +902,13 @@ hipError_t launch_persistent(const SolveArgs& a, int grid, hipStream_t s) {
   return hipGetLastError();
 }
 
+const void* rigid_kernel() { return (const void*)k_rigid; }
+
+hipError_t launch_rigid(const RigidArgs& a, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_rigid, dim3(grid), dim3(kWG), 0, s, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_reset_ctrl(int* ctrl, int n_ints, hipStream_t s) {
   hipLaunchKernelGGL(k_reset, dim3(grid_for((size_t)n_ints)), dim3(256), 0, s, ctrl, n_ints,
                      (const TaskDesc*)nullptr, 0);
@@ -701,6 +918,12 @@ hipError_t launch_reset_ctrl(int* ctrl, int n_ints, hipStream_t s) {
 hipError_t launch_reset_tasks(int* ctrl, int n_ints, const TaskDesc* tasks, int n_tasks, hipStream_t s) {
   const size_t n = (size_t)(n_ints > n_tasks ? n_ints : n_tasks);
   hipLaunchKernelGGL(k_reset, dim3(grid_for(n)), dim3(256), 0, s, ctrl, n_ints, tasks, n_tasks);
+  return hipGetLastError();
+}
+
+hipError_t launch_reset_rigid(int* ctrl, int n_ints, const RigidTask* tasks, int n_tasks, hipStream_t s) {
+  const size_t n = (size_t)(n_ints > n_tasks ? n_ints : n_tasks);
+  hipLaunchKernelGGL(k_reset_rigid, dim3(grid_for(n)), dim3(256), 0, s, ctrl, n_ints, tasks, n_tasks);
   return hipGetLastError();
 }
 
