@@ -14,7 +14,9 @@ between the pairwise phase and the scan levels from HIP events the library
 records around each persistent launch); the roofline of the dominant kernel
 (the persistent gradient-descent solver, same events); the dataflow mode
 (whole scan in one launch) and the plain one-launch-per-iteration path on
-the same GPU; and the CPU oracle timed on a bounded sample on the host cores.
+the same GPU; the same scan with the rigid normalized-cross-correlation
+operator on a rigidly moving lattice series of the same shape; and the CPU
+oracle timed on a bounded sample on the host cores.
 """
 from __future__ import annotations
 
@@ -46,6 +48,7 @@ def parse():
     ap.add_argument("--no-dataflow", action="store_true")
     ap.add_argument("--no-mock", action="store_true", help="skip the mock-operator scan microbenchmarks")
     ap.add_argument("--no-flex", action="store_true", help="skip the flexible-segment (Algorithm 1) scan")
+    ap.add_argument("--no-rigid", action="store_true", help="skip the rigid NCC operator scan")
     ap.add_argument("--cpu-sample", type=int, default=0, help="registrations in the oracle sample")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 3 device-to-device copies of MIB MiB (calibrates the HBM byte counters)")
@@ -89,6 +92,23 @@ def algorithmic_bytes(iters, n_pair, H, W, levels, max_iter):
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_persistent_series256-256x256-hier.traffic.json")
+
+
+# float64 operations of one rigid-operator pass over one pixel: the sample
+# position (12), the bilinear value and its two derivatives (23), the angle
+# derivative (9) and the 14 moment sums (5 additions, 9 fused multiply-adds).
+RIGID_FLOP_PER_PIXEL_PASS = 67
+PEAK_FP64_TFLOPS = 78.6
+
+
+def rigid_passes(iters, H, W, levels, max_iter):
+    """Pixel passes of the rigid solver: a level that stopped at iteration t
+    evaluated t + 1 times, a capped level max_iter times."""
+    import numpy as np
+    px = 0
+    for l in range(levels):
+        px += int(np.minimum(iters[:, l] + 1, max_iter).sum()) * (H >> l) * (W >> l)
+    return px
 
 
 def kernel_sources_sha256():
@@ -190,6 +210,61 @@ def mock_scan_report(rs):
             row["phases_ms"] = [round(x, 3) for x in ms[:3]]
         out.append(row)
     return {"elements": M, "workers": P, "mean_us": t, "runs": out}
+
+
+def rigid_report(rs, cfg, steps):
+    """The series scan with the rigid NCC operator on the same workload shape
+    (a lattice series under rigid motion, the same plan and stopping rule)."""
+    import torch
+    from dataclasses import replace
+
+    from synth import RIGID_TAU, rigid_series
+
+    import numpy as np
+    S = rigid_series(cfg.series)
+    p = replace(cfg.solver, tau=RIGID_TAU)
+    frames = S.frames.cuda()
+    N, H, W = frames.shape
+    M = N - 1
+    def run(mode):
+        rs.scan_run_rigid(frames, p, cfg.algo, cfg.chunk, cfg.global_algo, mode=mode)
+        torch.cuda.synchronize()
+        ts, kern = [], []
+        for _ in range(steps):
+            t1 = time.perf_counter()
+            out = rs.scan_run_rigid(frames, p, cfg.algo, cfg.chunk, cfg.global_algo, mode=mode)
+            launch = rs.last_solve_launch_ms()
+            torch.cuda.synchronize()
+            ts.append(1000.0 * (time.perf_counter() - t1))
+            kern.append(launch)
+        return out, ts, kern
+
+    mean = lambda xs: sum(xs) / len(xs)
+    _, ts_b, kern_b = run("batched")
+    (phi0, _, iters, status), ts, kern = run("dataflow")
+    iters = iters.cpu().numpy()
+    status = status.cpu().numpy()
+    kms = mean([sum(k) for k in kern])
+    n_launch = len(kern[0])
+    flop = RIGID_FLOP_PER_PIXEL_PASS * rigid_passes(iters, H, W, p.levels, p.max_iter)
+    achieved = flop / (kms / 1000.0) / 1e12
+    err = np.abs(phi0.cpu().numpy() - S.theta[1:])
+    r = math.sqrt(((W * W - 1) + (H * H - 1)) / 12.0)
+    return {"value": round(M / (mean(ts) / 1000.0), 3), "unit": "frames/s", "ms_per_step": round(mean(ts), 3),
+            "steps": steps, "registrations": int(len(iters)),
+            "mean_iterations_per_level": [round(float(x), 2) for x in iters.mean(axis=0)],
+            "maxiter_registrations": int((status & 1).sum()), "tau": p.tau,
+            "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
+                         "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None,
+                         "kernel": "k_rigid (batched rigid NCC solver)", "kernel_ms_per_step": round(kms, 3),
+                         "launches_per_step": n_launch, "kernel_ms_per_launch": round(kms / n_launch, 4),
+                         "flop_per_pixel_pass": RIGID_FLOP_PER_PIXEL_PASS, "flop_per_step": flop},
+            "vs_known_motion": {"max_translation_px": round(float(err[:, 1:].max()), 4),
+                                "max_angle_times_radius_px": round(float(err[:, 0].max()) * r, 4)},
+            "mode": "dataflow: the whole series in one persistent launch, device ready queue",
+            "batched": {"value": round(M / (mean(ts_b) / 1000.0), 3), "ms_per_step": round(mean(ts_b), 3),
+                        "kernel_ms_per_step": round(mean([sum(k) for k in kern_b]), 3),
+                        "mode": "one persistent launch for the pairwise phase and one per scan level"}}
 
 
 def main():
@@ -333,6 +408,9 @@ def main():
                           "segment_lengths": sorted(int(s_[1] - s_[0] + 1) for s_ in seg),
                           "mode": "reduce-then-scan, flexible segment boundaries (Algorithm 1), one group "
                                   "per worker"}
+
+    if not args.no_rigid:
+        result["rigid"] = rigid_report(rs, cfg, args.steps)
 
     if not args.no_plain:
         torch.cuda.synchronize()

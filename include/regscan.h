@@ -318,9 +318,13 @@ int reg_rigid_solve_batch(const float* frames, int N, int H, int W,
  *   phi0     [M][3] float64 out: theta_{0,k}, k = 1..M, M = N - 1
  *   pairs    [M][3] float64 out: theta_{k-1,k}, or NULL (kept in workspace)
  *   op_iters [M + n_ops][levels], status [M + n_ops]: as scan_run, or NULL
- * One persistent launch for the pairwise phase and one per plan level. */
+ *   mode     REG_BATCHED: one persistent launch for the pairwise phase and one
+ *            per plan level; REG_DATAFLOW: one launch for the whole series, a
+ *            registration starting as soon as its two inputs are done (the
+ *            results agree to rounding: the group size, and with it the order
+ *            of the moment sums, may differ). */
 int scan_run_rigid(const float* frames, int N, int H, int W, const reg_params_t* p,
-                   int algo, int chunk, int global_algo,
+                   int algo, int chunk, int global_algo, int mode,
                    double* phi0, double* pairs, int32_t* op_iters, int32_t* status, void* stream);
 
 /* Kernel-duration probe: total device time in milliseconds of the persistent

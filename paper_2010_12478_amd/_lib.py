@@ -92,7 +92,7 @@ _SIGS = {
     "scan_mock_run": (_I, [_I, _I, _I, _I, _I, _I, _P, _P, _P, _P, _P, _P]),
     "scan_run_flex": (_I, [_P, _I, _I, _I, _P, _I, _I, _P, _P, _P, _P, _P, _P, _P]),
     "reg_rigid_solve_batch": (_I, [_P, _I, _I, _I, _P, _P, _P, _P, _P, _P, _I, _P, _P]),
-    "scan_run_rigid": (_I, [_P, _I, _I, _I, _P, _I, _I, _I, _P, _P, _P, _P, _P]),
+    "scan_run_rigid": (_I, [_P, _I, _I, _I, _P, _I, _I, _I, _I, _P, _P, _P, _P, _P]),
 }
 
 

@@ -261,7 +261,7 @@ def rigid_solve_batch(frames, ref_idx, tmpl_idx, params, theta0=None):
     return theta, iters, status
 
 
-def scan_run_rigid(frames, params, algo="seq", chunk=0, global_algo="lf", want_pairs=True):
+def scan_run_rigid(frames, params, algo="seq", chunk=0, global_algo="lf", mode="batched", want_pairs=True):
     """Series registration with the rigid NCC operator.  Returns (phi0 [M][3],
     pairs [M][3] or None, op_iters [M + n_ops][L], status [M + n_ops])."""
     _need(frames, "frames")
@@ -276,8 +276,8 @@ def scan_run_rigid(frames, params, algo="seq", chunk=0, global_algo="lf", want_p
     status = torch.empty(M + n_ops, dtype=torch.int32, device=dev)
     p = params_struct(params)
     check(lib.scan_run_rigid(_ptr(frames), N, H, W, ctypes.byref(p), SCAN_ALGOS[algo], int(chunk),
-                             SCAN_ALGOS[global_algo], _ptr(phi0), _ptr(pairs), _ptr(iters), _ptr(status),
-                             _stream()))
+                             SCAN_ALGOS[global_algo], MODES[mode], _ptr(phi0), _ptr(pairs), _ptr(iters),
+                             _ptr(status), _stream()))
     return phi0, pairs, iters, status
 
 

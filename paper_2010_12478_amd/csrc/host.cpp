@@ -64,7 +64,7 @@ struct State {
   unsigned spin_limit = 1u << 22;   // ~seconds of polling before the watchdog aborts a run
   DevBuf pyr, slots, part, ctrl, tasks, nodes, upair, iters, status, misc, lvl, flow, mock;
   DevBuf flexw, flexn, flext, flexf;   // flexible-segment scan: worker state, pool, tasks, flow
-  DevBuf rnodes, rtasks, rpart, rctrl;   // rigid operator: parameters, descriptors, sums, queue
+  DevBuf rnodes, rtasks, rpart, rctrl, rflow;   // rigid operator: parameters, descriptors, sums, queue, DAG
   int rigid_blocks_per_cu = 0;
   double* h_E = nullptr;   // pinned host scalar for the plain path
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
@@ -1396,10 +1396,23 @@ int scan_run_flex(const float* frames, int N, int H, int W, const reg_params_t* 
 
 namespace {
 
+// Device arrays of a dataflow run (see SolveArgs): initial dependency counts
+// and ready queue, the consumers of every task, and the working copies.
+struct RigidFlow {
+  int* deps;
+  const int* deps0;
+  int* ready;
+  const int* ready0;
+  const int* cons_off;
+  const int* cons;
+  int n_ready0;
+};
+
 // Runs n rigid registrations (device descriptors) with one persistent launch:
 // groups of g workgroups on one XCD, g the largest power of two <= 16 that
-// keeps a group per task (rounded up to 8) resident.
-int run_rigid(RigidArgs a, const RigidTask* d_tasks, int n, hipStream_t s) {
+// keeps a group per startable task (all n, or in dataflow mode the initially
+// ready ones; rounded up to 8) resident.
+int run_rigid(RigidArgs a, const RigidTask* d_tasks, int n, const RigidFlow* f, hipStream_t s) {
   if (n == 0) return REG_OK;
   if (!g.rigid_blocks_per_cu) {
     int nb = 0;
@@ -1408,10 +1421,11 @@ int run_rigid(RigidArgs a, const RigidTask* d_tasks, int n, hipStream_t s) {
     g.rigid_blocks_per_cu = nb;
   }
   const int slots = g.rigid_blocks_per_cu * g.n_cu;
-  const int want = (n + 7) / 8 * 8;
+  const int want = ((f ? f->n_ready0 : n) + 7) / 8 * 8;
   int gs = 1;
   while (gs * 2 <= 16 && (long long)want * gs * 2 <= slots) gs *= 2;
-  int groups = std::min(want, std::max(8, slots / gs / 8 * 8));
+  int groups = std::max(8, slots / gs / 8 * 8);
+  if (!f) groups = std::min(want, groups);
   const int ctrl_ints = kCtrlHead + kCtrlGroup * groups;
   TRY(ensure(g.rctrl, (size_t)ctrl_ints * sizeof(int)));
   TRY(ensure(g.rpart, (size_t)groups * 2 * gs * 16 * sizeof(double)));
@@ -1422,6 +1436,14 @@ int run_rigid(RigidArgs a, const RigidTask* d_tasks, int n, hipStream_t s) {
   a.part = (double*)g.rpart.p;
   a.spin_limit = g.spin_limit;
   HIPCHK(launch_reset_rigid(a.ctrl, ctrl_ints, d_tasks, n, s));
+  if (f) {
+    a.dataflow = 1;
+    a.deps = f->deps;
+    a.ready = f->ready;
+    a.cons_off = f->cons_off;
+    a.cons = f->cons;
+    HIPCHK(launch_reset_dataflow(f->deps, f->deps0, f->ready, f->ready0, n, a.ctrl, f->n_ready0, s));
+  }
   hipEvent_t* ev = next_events();
   if (ev) HIPCHK(hipEventRecord(ev[0], s));
   HIPCHK(launch_rigid(a, groups * gs, s));
@@ -1490,16 +1512,18 @@ int reg_rigid_solve_batch(const float* frames, int N, int H, int W, const int32_
   }
   TRY(upload_rigid(tasks, s));
   g.events_used = 0;
-  return run_rigid(rigid_args(P, H, W, p), (const RigidTask*)g.rtasks.p, B, s);
+  return run_rigid(rigid_args(P, H, W, p), (const RigidTask*)g.rtasks.p, B, nullptr, s);
 }
 
 int scan_run_rigid(const float* frames, int N, int H, int W, const reg_params_t* p, int algo, int chunk,
-                   int global_algo, double* phi0, double* pairs, int32_t* op_iters, int32_t* status, void* stream) {
+                   int global_algo, int mode, double* phi0, double* pairs, int32_t* op_iters, int32_t* status,
+                   void* stream) {
   std::lock_guard<std::recursive_mutex> lk(g_mu);
   TRY(check_dims(1, H, W));
   TRY(check_params(p, H, W));
   if (N < 2) return fail(REG_E_INVALID, "a series needs N >= 2 frames (got %d)", N);
   if (!frames || !phi0) return fail(REG_E_INVALID, "NULL pointer");
+  if (mode != REG_BATCHED && mode != REG_DATAFLOW) return fail(REG_E_INVALID, "mode %d: REG_BATCHED or REG_DATAFLOW", mode);
   if (algo < SCAN_SEQ || algo > SCAN_HIER) return fail(REG_E_INVALID, "unknown scan algorithm %d", algo);
   if (algo == SCAN_HIER && (global_algo < SCAN_SEQ || global_algo > SCAN_BRENT_KUNG))
     return fail(REG_E_INVALID, "unknown global algorithm %d", global_algo);
@@ -1545,21 +1569,38 @@ int scan_run_rigid(const float* frames, int N, int H, int W, const reg_params_t*
     tasks[t].iters = op_iters ? op_iters + t * L : nullptr;
     tasks[t].status = status ? status + t : nullptr;
   }
-  // device descriptors grouped by level (stable), one launch per level
-  std::vector<int> order(tasks.size());
-  for (size_t t = 0; t < order.size(); ++t) order[t] = (int)t;
-  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return level_of[x] < level_of[y]; });
-  std::vector<RigidTask> sorted(tasks.size());
-  for (size_t t = 0; t < order.size(); ++t) sorted[t] = tasks[order[t]];
-  TRY(upload_rigid(sorted, s));
   const RigidArgs a = rigid_args(P, H, W, p);
   g.events_used = 0;
-  size_t first = 0;
-  while (first < sorted.size()) {
-    size_t last = first;
-    while (last < sorted.size() && level_of[order[last]] == level_of[order[first]]) ++last;
-    TRY(run_rigid(a, (const RigidTask*)g.rtasks.p + first, (int)(last - first), s));
-    first = last;
+  if (mode == REG_DATAFLOW) {
+    // one launch over the whole DAG: task id = node id (pairwise tasks are the
+    // elements, op q yields node M + q)
+    std::vector<std::vector<int>> dep(tasks.size());
+    for (size_t q = 0; q < n_ops; ++q) dep[M + q] = {plan[q].a, plan[q].b};
+    const TaskFlow tf = task_flow(dep);
+    const size_t T = tasks.size();
+    TRY(upload_rigid(tasks, s));
+    TRY(ensure(g.rflow, (tf.host.size() + 2 * T) * sizeof(int)));
+    HIPCHK(hipMemcpyAsync(g.rflow.p, tf.host.data(), tf.host.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));   // tf is host memory of this scope
+    const int* fl = (const int*)g.rflow.p;
+    int* work = (int*)g.rflow.p + tf.host.size();
+    const RigidFlow f{work, fl, work + T, fl + T, fl + 2 * T, fl + 3 * T + 1, tf.n_ready0};
+    TRY(run_rigid(a, (const RigidTask*)g.rtasks.p, (int)T, &f, s));
+  } else {
+    // device descriptors grouped by level (stable), one launch per level
+    std::vector<int> order(tasks.size());
+    for (size_t t = 0; t < order.size(); ++t) order[t] = (int)t;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return level_of[x] < level_of[y]; });
+    std::vector<RigidTask> sorted(tasks.size());
+    for (size_t t = 0; t < order.size(); ++t) sorted[t] = tasks[order[t]];
+    TRY(upload_rigid(sorted, s));
+    size_t first = 0;
+    while (first < sorted.size()) {
+      size_t last = first;
+      while (last < sorted.size() && level_of[order[last]] == level_of[order[first]]) ++last;
+      TRY(run_rigid(a, (const RigidTask*)g.rtasks.p + first, (int)(last - first), nullptr, s));
+      first = last;
+    }
   }
   HIPCHK(hipMemcpyAsync(phi0, node[0], 3 * sizeof(double), hipMemcpyDeviceToDevice, s));
   return REG_OK;

@@ -102,6 +102,13 @@ struct RigidArgs {
   int* ctrl;             // [0] ticket, [1] abort, per group at kCtrlHead + kCtrlGroup * id
   double* part;          // [groups][2][g][16]: per-member partial sums, by iteration parity
   unsigned spin_limit;
+  // dataflow mode (ctrl[2] / ctrl[3]: ready-queue head / tail): dependency
+  // counts, the ready queue (-1: not yet filled), consumers of every task
+  int dataflow;
+  int* deps;
+  int* ready;
+  const int* cons_off;
+  const int* cons;
 };
 const void* rigid_kernel();
 hipError_t launch_rigid(const RigidArgs& a, int grid, hipStream_t s);

@@ -639,19 +639,93 @@ __device__ __forceinline__ void rigid_compose(const double* t1, const double* t2
   out[2] = s * t1[1] + c * t1[2] + t2[2];
 }
 
+// One pixel of a rigid-operator pass: the sample position phi(x) from the
+// column terms (ca dx, sa dx) and the row's dy, the bilinear value of T and
+// its derivatives there, the angle derivative grad T . dphi/dalpha, and the 14
+// moment sums.  p_x = (t1 + c_x) + G_x and p_y = (t2 + c_y) + G_y with
+// t1 = ca dx - sa dy, t2 = sa dx + ca dy, dp/dalpha = (-t2, t1): at alpha = 0
+// the positions are formed exactly as the definition reads, so integer
+// translations land on the same cells on every evaluation.  The bilinear
+// value and its derivatives share the tap differences (b0, b1: the value
+// interpolated along x on the cell's upper and lower row; dT/dy = b1 - b0);
+// multiply-adds are fused (results agree with the definition-order
+// evaluation to rounding).
+__device__ __forceinline__ void rigid_pixel(const ReadBuf& rb, const ReadBuf& tb, int pitch, int w, int h, int x,
+                                            int y, double cadx, double sadx, double ca, double sa, double cx,
+                                            double cy, double gx, double gy, double* acc) {
+  const double dy = y - cy;
+  const double t1 = cadx - sa * dy;
+  const double t2 = sadx + ca * dy;
+  const double px = (t1 + cx) + gx;
+  const double py = (t2 + cy) + gy;
+  const double fx0 = floor(px), fy0 = floor(py);
+  const double fx = px - fx0, fy = py - fy0;
+  // the cell clamped to [-1, w-1] x [-1, h-1], offset by the border
+  const int cxi = (int)fmin(fmax(fx0, -1.0), (double)(w - 1)) + 1;
+  const int cyi = (int)fmin(fmax(fy0, -1.0), (double)(h - 1)) + 1;
+  const int o = __mul24(cyi, pitch) + cxi;
+  const double i00 = tb.f32(o, 0), i01 = tb.f32(o, 1);
+  const double i10 = tb.f32(o, pitch), i11 = tb.f32(o, pitch + 1);
+  const double av = rb.f32(__mul24(y, pitch) + x);
+  const double d0 = i01 - i00, d1 = i11 - i10;
+  const double b0 = i00 + fx * d0, b1 = i10 + fx * d1;
+  const double by = b1 - b0;
+  const double b = b0 + fy * by;
+  const double bx = d0 + fy * (d1 - d0);
+  const double ga = by * t1 - bx * t2;
+  acc[0] += av;
+  acc[1] += b;
+  acc[2] += av * av;
+  acc[3] += b * b;
+  acc[4] += av * b;
+  acc[5] += ga;
+  acc[6] += bx;
+  acc[7] += by;
+  acc[8] += av * ga;
+  acc[9] += av * bx;
+  acc[10] += av * by;
+  acc[11] += b * ga;
+  acc[12] += b * bx;
+  acc[13] += b * by;
+}
+
+// Next registration for the calling group's leader: the next ticket, or in
+// dataflow mode the next ready-queue slot once a finished registration has
+// filled it (n_tasks when none is left or the run was aborted).
+__device__ int rigid_next(const RigidArgs& a, int* abort_flag) {
+  if (!a.dataflow) return atomicAdd(a.ctrl, 1);
+  const int pos = __hip_atomic_fetch_add(&a.ctrl[2], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (pos >= a.n_tasks) return a.n_tasks;
+  unsigned spins = 0;
+  for (;;) {
+    const int t = ld_relaxed(&a.ready[pos]);
+    if (t >= 0) return t;
+    if (ld_relaxed(abort_flag)) return a.n_tasks;
+    if (++spins > a.spin_limit) {
+      __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return a.n_tasks;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+}
+
 // Rigid registration with normalized cross-correlation (the paper's operator,
 // Definition "Image registration problem", Section 2.3.1): phi(x) =
 // Rot(alpha)(x - c) + c + G about the image centre c, E = 1 - NCC(R, T o phi),
 // gradient flow in the metric diag(r^2, 1, 1) (r^2: mean squared pixel
 // distance from c) on the padded pyramid, G halved per coarser level.  A
-// group of g workgroups takes registrations from the ticket queue; per
+// group of g workgroups takes registrations from the ticket queue (or, in
+// dataflow mode, from the ready queue that finished registrations fill); per
 // iteration every member streams its rows once, accumulating in double the 14
 // sums that give NCC and its gradient (sum a, b, a^2, b^2, ab and per
 // parameter sum g_p, a g_p, b g_p, with g_p = grad T(phi(x)) . dphi/dtheta_p),
 // publishes them, and after the group barrier every thread adds the members'
-// sums in member order and takes the same step.
-__global__ void __launch_bounds__(kWG) k_rigid(RigidArgs a) {
-  __shared__ double red[kWG / kWave][16];
+// sums in member order and takes the same step.  Threads own columns (a
+// thread's column terms are computed once per iteration) and walk their rows
+// two at a time, so that a lone wavefront has independent work to issue.
+__global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) k_rigid(RigidArgs a) {
+  __shared__ double tacc[kRigidSums][kWG + 16];   // row padding: 2-way bank use on the strided reads
+  __shared__ double red[kRigidSums][17];
   __shared__ double s_sum[16];
   __shared__ int s_flag, s_task;
   const int xcd = blockIdx.x & 7, lb = blockIdx.x >> 3;
@@ -667,16 +741,31 @@ __global__ void __launch_bounds__(kWG) k_rigid(RigidArgs a) {
   G.local = false;
   int* abort_flag = a.ctrl + 1;
   double* part = a.part + (size_t)G.id * 2 * a.g * 16;
-  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x >> 6;
   int tpar = 0, par = 0;
+  if (threadIdx.x == 0) __hip_atomic_store(&G.xcc[G.member], xcc_id(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (G.member == 0 && threadIdx.x == 0)
-    __hip_atomic_store(&G.task[0], atomicAdd(a.ctrl, 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if (!group_sync(G, abort_flag, a.spin_limit, &s_flag)) return;
+    __hip_atomic_store(&G.task[0], rigid_next(a, abort_flag), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (!group_sync(G, abort_flag, a.spin_limit, &s_flag)) return;   // agent scope: always coherent
+  if (G.g > 1) {   // members on one XCD share its L2: the light barrier (see group_sync)
+    if (threadIdx.x == 0) {
+      int same = 1;
+      const int mine = __hip_atomic_load(&G.xcc[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      for (int m = 1; m < G.g; ++m)
+        same &= __hip_atomic_load(&G.xcc[m], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == mine;
+      s_task = same;
+    }
+    __syncthreads();
+    G.local = s_task != 0;
+    __syncthreads();
+  }
   for (;;) {
     if (threadIdx.x == 0) s_task = ld_relaxed(&G.task[tpar]);
     __syncthreads();
     const int t = s_task;
     if (t >= a.n_tasks) break;
+    // dataflow: the inputs were written by other groups, possibly on other
+    // XCDs, and published with an agent-scope release
+    if (a.dataflow) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     const RigidTask d = a.tasks[t];
     double th[3] = {0.0, 0.0, 0.0};
     if (d.kind == 1) rigid_compose(d.ta, d.tb, th);
@@ -702,7 +791,10 @@ __global__ void __launch_bounds__(kWG) k_rigid(RigidArgs a) {
       const double cx = (w - 1) / 2.0, cy = (h - 1) / 2.0;
       const double n = (double)h * w;
       const int row0 = (int)((long long)G.member * h / a.g), row1 = (int)((long long)(G.member + 1) * h / a.g);
-      const int p_end = (row1 - row0) * w;
+      // thread -> (column tx + k tw, rows ty, ty + rpi, ...) of the member's band
+      const int tw = w < kWG ? w : kWG, rpi = kWG / tw;
+      const int tx = threadIdx.x % tw, ty = threadIdx.x / tw;
+      const int y_first = ty < rpi ? row0 + ty : row1;
       double e_prev = 0.0;
       int it = 0;
       for (; it < a.max_iter; ++it) {
@@ -710,59 +802,39 @@ __global__ void __launch_bounds__(kWG) k_rigid(RigidArgs a) {
 #pragma unroll
         for (int j = 0; j < kRigidSums; ++j) acc[j] = 0.0;
         {
-#pragma clang fp contract(off)
           const double ca = cos(th[0]), sa = sin(th[0]);
-          int x = threadIdx.x % w, y = row0 + threadIdx.x / w;
-          for (int q = threadIdx.x; q < p_end; q += kWG) {
-            const double dx = x - cx, dy = y - cy;
-            const double px = ca * dx - sa * dy + cx + th[1];
-            const double py = sa * dx + ca * dy + cy + th[2];
-            const double fx0 = floor(px), fy0 = floor(py);
-            const double fx = px - fx0, fy = py - fy0;
-            // the cell clamped to [-1, w-1] x [-1, h-1], offset by the border
-            const int cxi = (int)fmin(fmax(fx0, -1.0), (double)(w - 1)) + 1;
-            const int cyi = (int)fmin(fmax(fy0, -1.0), (double)(h - 1)) + 1;
-            const int o = __mul24(cyi, pitch) + cxi;
-            const double i00 = tb.f32(o, 0), i01 = tb.f32(o, 1);
-            const double i10 = tb.f32(o, pitch), i11 = tb.f32(o, pitch + 1);
-            const double av = rb.f32(__mul24(y, pitch) + x);
-            const double ox = 1.0 - fx, oy = 1.0 - fy;
-            const double b = oy * (ox * i00 + fx * i01) + fy * (ox * i10 + fx * i11);
-            const double bx = oy * (i01 - i00) + fy * (i11 - i10);
-            const double by = ox * (i10 - i00) + fx * (i11 - i01);
-            const double ga = bx * (-sa * dx - ca * dy) + by * (ca * dx - sa * dy);
-            acc[0] += av;
-            acc[1] += b;
-            acc[2] = fma(av, av, acc[2]);
-            acc[3] = fma(b, b, acc[3]);
-            acc[4] = fma(av, b, acc[4]);
-            acc[5] += ga;
-            acc[6] += bx;
-            acc[7] += by;
-            acc[8] = fma(av, ga, acc[8]);
-            acc[9] = fma(av, bx, acc[9]);
-            acc[10] = fma(av, by, acc[10]);
-            acc[11] = fma(b, ga, acc[11]);
-            acc[12] = fma(b, bx, acc[12]);
-            acc[13] = fma(b, by, acc[13]);
-            x += kWG;
-            while (x >= w) {
-              x -= w;
-              ++y;
+          for (int x = tx; x < w; x += tw) {
+            const double dx = x - cx;
+            const double cadx = ca * dx, sadx = sa * dx;
+            int y = y_first;
+            for (; y + rpi < row1; y += 2 * rpi) {
+              rigid_pixel(rb, tb, pitch, w, h, x, y, cadx, sadx, ca, sa, cx, cy, th[1], th[2], acc);
+              rigid_pixel(rb, tb, pitch, w, h, x, y + rpi, cadx, sadx, ca, sa, cx, cy, th[1], th[2], acc);
             }
+            if (y < row1) rigid_pixel(rb, tb, pitch, w, h, x, y, cadx, sadx, ca, sa, cx, cy, th[1], th[2], acc);
           }
         }
-        // member partial sums: butterfly per wavefront, then the 4 wavefronts
+        // member partial sums through LDS: every thread's 14 sums, then 16
+        // threads per sum add 16 threads' values each (stride 16), then one
+        // thread per sum adds those 16 partials
 #pragma unroll
-        for (int j = 0; j < kRigidSums; ++j) {
-          const double v = wave_sum(acc[j]);
-          if (lane == 0) red[wave][j] = v;
+        for (int j = 0; j < kRigidSums; ++j) tacc[j][threadIdx.x] = acc[j];
+        __syncthreads();
+        if (threadIdx.x < kRigidSums * 16) {
+          const int j = threadIdx.x >> 4, q = threadIdx.x & 15;
+          double v = 0.0;
+#pragma unroll
+          for (int k = 0; k < kWG / 16; ++k) v += tacc[j][q + 16 * k];
+          red[j][q] = v;
         }
         __syncthreads();
         double* pp = part + (size_t)par * a.g * 16;
-        if (threadIdx.x < kRigidSums)
-          pp[G.member * 16 + threadIdx.x] =
-              ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
+        if (threadIdx.x < kRigidSums) {
+          double v = 0.0;
+#pragma unroll
+          for (int q = 0; q < 16; ++q) v += red[threadIdx.x][q];
+          pp[G.member * 16 + threadIdx.x] = v;
+        }
         if (!group_sync(G, abort_flag, a.spin_limit, &s_flag)) return;
         if (threadIdx.x < kRigidSums) {
           const SharedBuf pb(pp);
@@ -814,7 +886,19 @@ __global__ void __launch_bounds__(kWG) k_rigid(RigidArgs a) {
       if (d.iters)
         for (int l = 0; l < a.levels; ++l) d.iters[l] = iters[l];
       if (d.status) *d.status = status;
-      __hip_atomic_store(&G.task[tpar ^ 1], atomicAdd(a.ctrl, 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (a.dataflow) {
+        // publish the parameters device-wide, then release the consumers whose
+        // last input they were
+        __threadfence();
+        for (int q = a.cons_off[t]; q < a.cons_off[t + 1]; ++q) {
+          const int c = a.cons[q];
+          if (__hip_atomic_fetch_add(&a.deps[c], -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 1) {
+            const int pos = __hip_atomic_fetch_add(&a.ctrl[3], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&a.ready[pos], c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          }
+        }
+      }
+      __hip_atomic_store(&G.task[tpar ^ 1], rigid_next(a, abort_flag), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     tpar ^= 1;
     if (!group_sync(G, abort_flag, a.spin_limit, &s_flag)) return;

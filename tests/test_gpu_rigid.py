@@ -148,9 +148,9 @@ def test_batch_larger_than_the_resident_groups(rs):
     assert set(status.tolist()) <= {0, 1}
 
 
-def _check_scan(rs, S, p, algo, chunk=0, global_algo="lf"):
+def _check_scan(rs, S, p, algo, chunk=0, global_algo="lf", mode="batched"):
     M = S.frames.shape[0] - 1
-    phi0, pairs, iters, status = rs.scan_run_rigid(S.frames.cuda(), p, algo, chunk, global_algo)
+    phi0, pairs, iters, status = rs.scan_run_rigid(S.frames.cuda(), p, algo, chunk, global_algo, mode=mode)
     ops, _ = plans.make_plan(M, algo, chunk, global_algo)
     w_phi0, w_pairs, w_iters = orig.run_scan(S.frames.double().numpy(), p, ops, M)
     H, W = S.frames.shape[1:]
@@ -160,13 +160,14 @@ def _check_scan(rs, S, p, algo, chunk=0, global_algo="lf"):
     assert ((host(status) & 6) == 0).all()
 
 
+@pytest.mark.parametrize("mode", ["batched", "dataflow"])
 @pytest.mark.parametrize("algo,chunk", [("seq", 0), ("dissemination", 0), ("lf", 0), ("bk", 0), ("hier", 3)])
-def test_scan_matches_oracle(rs, algo, chunk):
-    announce(f"rigid scan {algo}")
+def test_scan_matches_oracle(rs, algo, chunk, mode):
+    announce(f"rigid scan {algo} {mode}")
     cfg = get_config(1, n_frames=11)
     S = rigid_series(cfg.series)
     p = SolverParams(levels=2, max_iter=200, tau=RIGID_TAU)
-    _check_scan(rs, S, p, algo, chunk)
+    _check_scan(rs, S, p, algo, chunk, mode=mode)
 
 
 def test_scan_two_frames_and_ragged_size(rs):
@@ -175,19 +176,27 @@ def test_scan_two_frames_and_ragged_size(rs):
     _check_scan(rs, S, SolverParams(levels=2, max_iter=100, tau=RIGID_TAU), "lf")
     S = rigid_series(SeriesSpec(6, 40, 56, noise=0.05, seed=53))
     _check_scan(rs, S, SolverParams(levels=1, max_iter=100, tau=RIGID_TAU), "hier", 2, "bk")
+    _check_scan(rs, S, SolverParams(levels=1, max_iter=100, tau=RIGID_TAU), "hier", 2, "bk", mode="dataflow")
 
 
-def test_full_size_series_sampled(rs):
+def test_scan_invalid_mode(rs):
+    S = rigid_series(SeriesSpec(3, 32, 32, noise=0.05, seed=59))
+    with pytest.raises(rs.RegError):
+        rs.scan_run_rigid(S.frames.cuda(), SolverParams(levels=1, max_iter=5, tau=RIGID_TAU), "lf", mode="plain")
+
+
+@pytest.mark.parametrize("mode", ["batched", "dataflow"])
+def test_full_size_series_sampled(rs, mode):
     """The 256-frame 256x256 series with the hierarchical plan (chunk 4,
     Ladner-Fischer global phase): sampled pairwise results, and sampled
     prefixes (0, k) that the plan forms from a prefix (0, j) and the element
     (j, k), each recomputed by the oracle from the GPU's own inputs."""
-    announce("rigid full-size series256-256x256-hier")
+    announce(f"rigid full-size series256-256x256-hier {mode}")
     cfg = get_config(2)
     S = rigid_series(cfg.series)
     p = replace(cfg.solver, tau=RIGID_TAU)
     M = cfg.series.n_frames - 1
-    phi0, pairs, iters, status = rs.scan_run_rigid(S.frames.cuda(), p, "hier", 4, "lf")
+    phi0, pairs, iters, status = rs.scan_run_rigid(S.frames.cuda(), p, "hier", 4, "lf", mode=mode)
     phi0, pairs, iters, status = host(phi0), host(pairs), host(iters), host(status)
     assert ((status & 6) == 0).all()
     ops, _ = plans.make_plan(M, "hier", 4, "lf")
