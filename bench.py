@@ -4,19 +4,20 @@ Workload: 256 synthetic 256x256 lattice frames (drift <= 4 px, noise 0.1), a
 2-level pyramid, relative-decrease stopping (1e-5, at most 200 iterations per
 level), the hierarchical reduce-then-scan plan (chunks of 4 elements,
 Ladner-Fischer global phase).  One step = frame pyramid + the 255 pairwise
-registrations + every scan level through scan_run in batched mode: one
-persistent launch for the pairwise phase and one per scan level, the whole
-schedule replayed from a captured hipGraph; inputs resident in HBM.
+registrations + every scan op through scan_run in dataflow mode: one
+persistent launch in which an op starts as soon as its two inputs are done,
+replayed from a captured hipGraph; inputs resident in HBM.
 
 Prints one JSON line: frames registered per second over the K timed steps
-(with the per-step times and their 95% confidence interval, and the split
-between the pairwise phase and the scan levels from HIP events the library
-records around each persistent launch); the roofline of the dominant kernel
-(the persistent gradient-descent solver, same events); the dataflow mode
-(whole scan in one launch) and the plain one-launch-per-iteration path on
-the same GPU; the same scan with the rigid normalized-cross-correlation
-operator on a rigidly moving lattice series of the same shape; and the CPU
-oracle timed on a bounded sample on the host cores.
+(with the per-step times and their 95% confidence interval); the roofline of
+the dominant kernel (the persistent gradient-descent solver, timed with HIP
+events the library records around its launch); the level-synchronous form
+(one launch per scan level), the flexible-segment reduce-then-scan
+(Algorithm 1) and the plain one-launch-per-iteration path on the same GPU;
+the same scan with the rigid normalized-cross-correlation operator on a
+rigidly moving lattice series of the same shape; the mock-operator scan
+microbenchmarks; and the CPU oracle timed on a bounded sample on the host
+cores.
 """
 from __future__ import annotations
 
@@ -45,7 +46,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
-    ap.add_argument("--no-dataflow", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the level-synchronous comparison")
     ap.add_argument("--no-mock", action="store_true", help="skip the mock-operator scan microbenchmarks")
     ap.add_argument("--no-flex", action="store_true", help="skip the flexible-segment (Algorithm 1) scan")
     ap.add_argument("--no-rigid", action="store_true", help="skip the rigid NCC operator scan")
@@ -314,26 +315,32 @@ def main():
                status=torch.empty(n_regs, dtype=torch.int32, device=dev))
     rs.set_tuning(TILE_ROWS, MAX_GROUP, resident=True)
 
-    def step(mode="batched", graph=True):
+    def step(mode, graph):
         rs.scan_run(frames, p, cfg.algo, cfg.chunk, cfg.global_algo, mode=mode, graph=graph, out=out)
 
-    for _ in range(args.warmup):     # the first call also captures the graph
-        step()
-    torch.cuda.synchronize()
-    step_ms, pair_ms, scan_ms, kern_ms, kern_launches = [], [], [], 0.0, 0
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        ts = time.perf_counter()
-        step()
-        launch = rs.last_solve_launch_ms()      # waits for this step's solver events
+    def timed(mode, graph, steps, warmup):
+        """warmup untimed calls (the first also captures the graph), then
+        `steps` calls each fenced by a device synchronisation; per call the
+        wall time and the solver launches' durations (HIP events)."""
+        for _ in range(warmup):
+            step(mode, graph)
         torch.cuda.synchronize()
-        step_ms.append(1000.0 * (time.perf_counter() - ts))
-        pair_ms.append(launch[0])
-        scan_ms.append(sum(launch[1:]))
-        kern_ms += sum(launch)
-        kern_launches += len(launch)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+        step_ms, launches = [], []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            ts = time.perf_counter()
+            step(mode, graph)
+            launch = rs.last_solve_launch_ms()      # waits for this step's solver events
+            torch.cuda.synchronize()
+            step_ms.append(1000.0 * (time.perf_counter() - ts))
+            launches.append(launch)
+        torch.cuda.synchronize()
+        return step_ms, launches, time.perf_counter() - t0
+
+    mean = lambda xs: sum(xs) / len(xs)
+    step_ms, launches, wall = timed("dataflow", True, args.steps, args.warmup)
+    kern_ms = sum(sum(l) for l in launches)
+    kern_launches = sum(len(l) for l in launches)
     ms_per_step = 1000.0 * wall / args.steps
     iters = out["iters"].cpu().numpy()
     status = out["status"].cpu().numpy()
@@ -341,7 +348,6 @@ def main():
     alg_bytes = alg_step * args.steps
     achieved = alg_bytes / (kern_ms / 1000.0) / 1e9
     value = M / (ms_per_step / 1000.0)
-    mean = lambda xs: sum(xs) / len(xs)
 
     result = {
         "metric": METRIC, "value": round(value, 3), "unit": "frames/s", "n_gpus": 1,
@@ -353,18 +359,18 @@ def main():
                    "plan_ops": int(len(ops)), "plan_levels": int(n_levels),
                    "registrations": int(n_regs), "max_iter": p.max_iter, "rel_tol": p.rel_tol,
                    "tau": p.tau, "lambda": p.lam, "storage": "f32", "parallelism": "single-gpu",
-                   "execution": "batched: one persistent launch per scan level, replayed from a hipGraph",
+                   "execution": "dataflow: pairwise registrations and every scan op in one persistent launch, "
+                                "an op started as soon as its inputs are done (device ready queue); "
+                                "replayed from a hipGraph",
                    "tile_rows": TILE_ROWS, "max_group": MAX_GROUP,
                    "mean_iterations_per_level": [round(float(x), 2) for x in iters.mean(axis=0)],
                    "maxiter_registrations": int((status & 1).sum()),
                    "aborted_registrations": int((status & 4).sum())},
         "step_ms": [round(x, 3) for x in step_ms],
         "step_ms_ci95": None if ci95(step_ms) is None else round(ci95(step_ms), 3),
-        "phases_ms": {"pairwise": round(mean(pair_ms), 3), "scan_levels": round(mean(scan_ms), 3),
-                      "scan_only_frames_per_s": round(M / (mean(scan_ms) / 1000.0), 3)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": measured_traffic(),
-                     "kernel": "k_persistent (batched gradient-descent solver)",
+                     "kernel": "k_persistent (gradient-descent solver, dataflow)",
                      "kernel_ms_per_step": round(kern_ms / args.steps, 3),
                      "launches_per_step": kern_launches // max(1, args.steps),
                      "kernel_ms_per_launch": round(kern_ms / max(1, kern_launches), 4),
@@ -373,18 +379,20 @@ def main():
         "cpu_baseline": base,
     }
 
-    if not args.no_dataflow:
-        step("dataflow", False)
-        torch.cuda.synchronize()
-        ts = []
-        for _ in range(args.steps):
-            t1 = time.perf_counter()
-            step("dataflow", False)
-            torch.cuda.synchronize()
-            ts.append(1000.0 * (time.perf_counter() - t1))
-        result["dataflow"] = {"value": round(M / (mean(ts) / 1000.0), 3), "unit": "frames/s",
-                              "ms_per_step": round(mean(ts), 3), "steps": args.steps,
-                              "mode": "whole scan in one persistent launch, device ready queue"}
+    if not args.no_batched:
+        # the level-synchronous form: one persistent launch for the pairwise
+        # phase and one per scan level, from a hipGraph
+        ts_b, launch_b, wall_b = timed("batched", True, args.steps, 1)
+        kb = sum(sum(l) for l in launch_b)
+        result["batched"] = {"value": round(M / (wall_b / args.steps), 3), "unit": "frames/s",
+                             "ms_per_step": round(1000.0 * wall_b / args.steps, 3), "steps": args.steps,
+                             "kernel_ms_per_step": round(kb / args.steps, 3),
+                             "launches_per_step": len(launch_b[0]),
+                             "roofline_frac": round(alg_step * args.steps / (kb / 1000.0) / 1e9 / PEAK_HBM_GBS, 4),
+                             "phases_ms": {"pairwise": round(mean([l[0] for l in launch_b]), 3),
+                                           "scan_levels": round(mean([sum(l[1:]) for l in launch_b]), 3)},
+                             "mode": "one persistent launch for the pairwise phase and one per scan level, "
+                                     "replayed from a hipGraph"}
 
     if not args.no_flex:
         # the reduce-then-scan with flexible segment boundaries (Algorithm 1)

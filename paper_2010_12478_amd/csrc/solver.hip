@@ -273,7 +273,7 @@ __device__ __forceinline__ float* start_buffer(const SolveArgs& a, const TaskDes
 }
 
 // Runs one registration with the calling group.  Returns false on abort.
-__device__ bool run_task(const SolveArgs& a, const TaskDesc& d, Group& G, float* slot, double* part, int& par,
+__device__ __forceinline__ bool run_task(const SolveArgs& a, const TaskDesc& d, Group& G, float* slot, double* part, int& par,
                          double* red, double* s_E, int* s_flag, float2* roll) {
   int* abort_flag = a.ctrl + 1;
   const int L = a.levels;
@@ -523,6 +523,9 @@ __device__ int flex_next(const SolveArgs& a, Group& G, FlexState& F, TaskDesc& d
   return 1;
 }
 
+// FLEX: the flexible-segment phase 1 (a separate instantiation, so that the
+// other modes carry none of its state).
+template <bool FLEX>
 __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) k_persistent(SolveArgs a) {
   __shared__ double red[kWG / kWave];
   __shared__ double s_E;
@@ -566,7 +569,7 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) k
   }
   FlexState F{0, 0, 0, 0};
   __shared__ unsigned long long s_desc[8];
-  if (a.flex) {
+  if constexpr (FLEX) {
     if (G.id >= a.flex_workers) return;   // groups come in multiples of 8: the surplus has no segment
     F.pl = F.pr = a.starts[G.id];
     if (G.member == 0 && threadIdx.x == 0) F.t0 = wall_clock64();
@@ -574,7 +577,7 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) k
   for (;;) {
     TaskDesc d;
     int t = 0;
-    if (a.flex) {
+    if constexpr (FLEX) {
       const int r = flex_next(a, G, F, d, &s_flag, s_desc);
       if (r < 0) return;
       if (r == 0) break;
@@ -589,7 +592,7 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) k
       d = a.tasks[t];
     }
     if (!run_task(a, d, G, slot, part, par, red, &s_E, &s_flag, roll)) return;
-    if (a.flex) {
+    if constexpr (FLEX) {
       if (!group_sync(G, abort_flag, a.spin_limit, &s_flag)) return;
       if (G.member == 0 && threadIdx.x == 0) {
         ++F.ops;
@@ -619,7 +622,7 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) k
                          __HIP_MEMORY_SCOPE_AGENT);
     if (!group_sync(G, abort_flag, a.spin_limit, &s_flag)) return;
   }
-  if (a.flex && G.member == 0 && threadIdx.x == 0) {
+  if (FLEX && G.member == 0 && threadIdx.x == 0) {
     a.flex_seg[G.id * 4 + 0] = F.pl;
     a.flex_seg[G.id * 4 + 1] = F.pr;
     a.flex_seg[G.id * 4 + 2] = F.ops;
@@ -979,10 +982,13 @@ inline int grid_for(size_t n) {
 
 }  // namespace
 
-const void* persistent_kernel() { return (const void*)k_persistent; }
+const void* persistent_kernel() { return (const void*)k_persistent<false>; }
 
 hipError_t launch_persistent(const SolveArgs& a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_persistent, dim3(grid), dim3(kWG), 0, s, a);
+  if (a.flex)
+    hipLaunchKernelGGL(k_persistent<true>, dim3(grid), dim3(kWG), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_persistent<false>, dim3(grid), dim3(kWG), 0, s, a);
   return hipGetLastError();
 }
 

@@ -148,10 +148,12 @@ def _reg(args):
 
 def test_full_size_series256_sampled_prefixes(rs):
     """256 frames of 256x256, 2 levels, hierarchical plan (chunks of 4,
-    Ladner-Fischer global phase) in the benchmark's launch configuration.
-    The oracle recomputes, in the plan's combination order, the prefixes
-    phi_{0,1..6} of the first chunk, and the independent pairwise
-    registrations u_{k-1,k} for a sample of k across the series."""
+    Ladner-Fischer global phase) in the benchmark's launch configuration
+    (dataflow, replayed from a hipGraph: the first call captures, the second
+    replays), which must equal the level-synchronous run bitwise.  The oracle
+    recomputes, in the plan's combination order, the prefixes phi_{0,1..6} of
+    the first chunk, and the independent pairwise registrations u_{k-1,k} for
+    a sample of k across the series."""
     announce("full size series256")
     from concurrent.futures import ProcessPoolExecutor
     import multiprocessing as mp
@@ -161,8 +163,19 @@ def test_full_size_series256_sampled_prefixes(rs):
     p = cfg.solver
     rs.set_tuning(64, 64, resident=True)   # the library defaults, which the benchmark runs with
     try:
-        phi0, u_pair, iters, status = (host(t) for t in rs.scan_run(frames.cuda(), p, cfg.algo, cfg.chunk,
-                                                                     cfg.global_algo, mode="batched"))
+        fr = frames.cuda()
+        lvl = [t.clone() for t in rs.scan_run(fr, p, cfg.algo, cfg.chunk, cfg.global_algo, mode="batched")]
+        M = frames.shape[0] - 1
+        out = dict(phi0=torch.empty_like(lvl[0]), u_pair=torch.empty_like(lvl[1]),
+                   iters=torch.empty_like(lvl[2]), status=torch.empty_like(lvl[3]))
+        for rep in range(2):
+            for t in out.values():
+                t.fill_(-7)
+            rs.scan_run(fr, p, cfg.algo, cfg.chunk, cfg.global_algo, mode="dataflow", graph=True, out=out)
+            torch.cuda.synchronize()
+            for want, got in zip(lvl, (out["phi0"], out["u_pair"], out["iters"], out["status"])):
+                assert torch.equal(want, got), rep
+        phi0, u_pair, iters, status = (host(out[k]) for k in ("phi0", "u_pair", "iters", "status"))
     finally:
         rs.set_tuning(16, 32)
     M = frames.shape[0] - 1
