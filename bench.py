@@ -257,7 +257,7 @@ def rigid_report(rs, cfg, steps):
             "maxiter_registrations": int((status & 1).sum()), "tau": p.tau,
             "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS,
                          "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None,
-                         "kernel": "k_rigid (batched rigid NCC solver)", "kernel_ms_per_step": round(kms, 3),
+                         "kernel": "k_rigid (rigid NCC solver, dataflow)", "kernel_ms_per_step": round(kms, 3),
                          "launches_per_step": n_launch, "kernel_ms_per_launch": round(kms / n_launch, 4),
                          "flop_per_pixel_pass": RIGID_FLOP_PER_PIXEL_PASS, "flop_per_step": flop},
             "vs_known_motion": {"max_translation_px": round(float(err[:, 1:].max()), 4),

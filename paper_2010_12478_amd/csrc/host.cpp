@@ -1409,9 +1409,12 @@ struct RigidFlow {
 };
 
 // Runs n rigid registrations (device descriptors) with one persistent launch:
-// groups of g workgroups on one XCD, g the largest power of two <= 16 that
-// keeps a group per startable task (all n, or in dataflow mode the initially
-// ready ones; rounded up to 8) resident.
+// groups of g workgroups on one XCD.  Level-synchronous: g the largest power
+// of two <= 16 that keeps a group per task (rounded up to 8) resident.
+// Dataflow: the number of ready registrations varies over the run and the
+// slowest ones set its end, so g is sized for the registration instead:
+// about 32 fine-level pixels per thread and pass (at 256x256, g = 8 measured
+// 27% faster than g = 4 and 13% faster than g = 16), all slots filled.
 int run_rigid(RigidArgs a, const RigidTask* d_tasks, int n, const RigidFlow* f, hipStream_t s) {
   if (n == 0) return REG_OK;
   if (!g.rigid_blocks_per_cu) {
@@ -1421,9 +1424,12 @@ int run_rigid(RigidArgs a, const RigidTask* d_tasks, int n, const RigidFlow* f, 
     g.rigid_blocks_per_cu = nb;
   }
   const int slots = g.rigid_blocks_per_cu * g.n_cu;
-  const int want = ((f ? f->n_ready0 : n) + 7) / 8 * 8;
+  const int want = (n + 7) / 8 * 8;
   int gs = 1;
-  while (gs * 2 <= 16 && (long long)want * gs * 2 <= slots) gs *= 2;
+  if (f)
+    while (gs * 2 <= 16 && (long long)a.H * a.W >= (long long)gs * 2 * kWG * 32 && 8 * gs * 2 <= slots) gs *= 2;
+  else
+    while (gs * 2 <= 16 && (long long)want * gs * 2 <= slots) gs *= 2;
   int groups = std::max(8, slots / gs / 8 * 8);
   if (!f) groups = std::min(want, groups);
   const int ctrl_ints = kCtrlHead + kCtrlGroup * groups;
