@@ -14,6 +14,13 @@ constexpr int kRB = 2;          // rows per register batch in the sweep
 constexpr int kMaxRPT = 16;     // rows per thread of a register-resident tile at most (tile height 64)
 
 __host__ __device__ inline int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
+// clampi(v, 0, hi) as one v_med3_i32 (the compiler forms it only for
+// immediate bounds); hi is wave-uniform.
+__device__ __forceinline__ int clamp0(int v, int hi) {
+  int r;
+  asm("v_med3_i32 %0, %1, 0, %2" : "=v"(r) : "v"(v), "s"(hi));
+  return r;
+}
 
 // Stopping rule of a level (relative energy decrease), shared by the device
 // solver and the host loop of the plain path so both decide identically.

@@ -97,8 +97,14 @@ __device__ __forceinline__ double resident_step(const ResidentTile& P, float (&s
                                                 const ReadBuf& cnext, const ReadBuf& tb, const ReadBuf& rb,
                                                 float2* roll) {
   // P.h, P.w, P.xt, P.y0 are wave-uniform: row offsets go to the scalar
-  // offset of the buffer instructions, the per-lane offset is the lane
-  const int h = P.h, w = P.w, hw = P.hw, y0 = P.y0, xt = P.xt, pitch = P.pitch;
+  // offset of the buffer instructions, the per-lane offset is the lane.
+  // y0 and pitch are made opaque per iteration so that the per-row offsets
+  // are recomputed (a few scalar instructions) instead of being hoisted out
+  // of the level loop, where they outnumber the scalar registers and were
+  // spilled to vector-register lanes and read back row by row.
+  const int h = P.h, w = P.w, hw = P.hw, xt = P.xt;
+  int y0 = P.y0, pitch = P.pitch;
+  asm volatile("" : "+s"(y0), "+s"(pitch));
   // per-lane values derived afresh every iteration rather than held in
   // registers across the level (the empty asm hides their invariance)
   int lane = P.lane;
@@ -137,7 +143,7 @@ __device__ __forceinline__ double resident_step(const ResidentTile& P, float (&s
     fly[r] = floor_cell(sy[r], iy);
     // the cell clamped to [-1, w-1] x [-1, h-1], offset by the border: the
     // four taps are o, o + 1, o + pitch, o + pitch + 1
-    const int o = __mul24(clampi(y0 + r + iy + 1, 0, h), pitch) + clampi(x + ix + 1, 0, w);
+    const int o = __mul24(clamp0(y0 + r + iy + 1, h), pitch) + clamp0(x + ix + 1, w);
     taps[r][0] = tb.f32(o, 0);
     taps[r][1] = tb.f32(o, 1);
     taps[r][2] = tb.f32(o, pitch);

@@ -805,7 +805,8 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) k
 #pragma unroll
         for (int j = 0; j < kRigidSums; ++j) acc[j] = 0.0;
         {
-          const double ca = cos(th[0]), sa = sin(th[0]);
+          double sa, ca;
+          sincos(th[0], &sa, &ca);
           for (int x = tx; x < w; x += tw) {
             const double dx = x - cx;
             const double cadx = ca * dx, sadx = sa * dx;
@@ -857,11 +858,14 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) k
             E = 1.0;
             g0 = g1 = g2 = 0.0;
           } else {
+            // one reciprocal each for the two denominators (a division is a
+            // long dependent sequence, and every iteration waits for these)
             const double den = sqrt(saa * sbb), ncc = sab / den;
+            const double rden = 1.0 / den, q = ncc / sbb;
             E = 1.0 - ncc;
-            g0 = -((s_sum[8] - abar * s_sum[5]) / den - ncc * (s_sum[11] - bbar * s_sum[5]) / sbb);
-            g1 = -((s_sum[9] - abar * s_sum[6]) / den - ncc * (s_sum[12] - bbar * s_sum[6]) / sbb);
-            g2 = -((s_sum[10] - abar * s_sum[7]) / den - ncc * (s_sum[13] - bbar * s_sum[7]) / sbb);
+            g0 = -((s_sum[8] - abar * s_sum[5]) * rden - (s_sum[11] - bbar * s_sum[5]) * q);
+            g1 = -((s_sum[9] - abar * s_sum[6]) * rden - (s_sum[12] - bbar * s_sum[6]) * q);
+            g2 = -((s_sum[10] - abar * s_sum[7]) * rden - (s_sum[13] - bbar * s_sum[7]) * q);
           }
         }
         if (!isfinite(E)) {
