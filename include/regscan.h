@@ -337,7 +337,10 @@ int reg_last_solve_timing(double* total_ms, int* launches);
 /* The same probe per launch, in launch order (for scan_run in REG_BATCHED
  * mode: the pairwise phase, then one launch per scan level): up to `cap`
  * durations in milliseconds into ms[] (HOST), the number of launches into
- * *n.  A replayed graph (SCAN_F_GRAPH) records these events itself. */
+ * *n.  A call that replays a graph (SCAN_F_GRAPH) reports one duration, that
+ * of the whole replay (pyramid, resets and every solver launch), from an
+ * event pair recorded around it; the call that captures the graph runs the
+ * launches directly and reports them one by one. */
 int reg_last_solve_launch_ms(double* ms, int cap, int* n);
 
 /* Prefix scan with an artificial operator (Section 5, microbenchmarks): the

@@ -73,7 +73,6 @@ struct State {
     std::string key;
     unsigned generation;
     hipGraphExec_t exec;
-    size_t n_events;      // timing event pairs recorded by a replay (pool entries 0..n-1)
     DevBuf tasks, flow;   // descriptors owned by the graph
   };
   std::vector<Graph> graphs;
@@ -930,9 +929,13 @@ int scan_run(const float* frames, int N, int H, int W, const reg_params_t* p, in
     }
     for (auto& gr : g.graphs) {
       if (gr.key == key && gr.generation == g.generation) {
-        // the graph records the timing events of its solver launches itself
+        // timing: one event pair around the whole replay (event records
+        // captured inside a graph are not re-recorded when it is replayed)
+        g.events_used = 0;
+        hipEvent_t* ev = next_events();
+        if (ev) HIPCHK(hipEventRecord(ev[0], s));
         HIPCHK(hipGraphLaunch(gr.exec, s));
-        g.events_used = gr.n_events;
+        if (ev) HIPCHK(hipEventRecord(ev[1], s));
         return REG_OK;
       }
     }
@@ -1021,9 +1024,9 @@ int scan_run(const float* frames, int N, int H, int W, const reg_params_t* p, in
   hipStream_t cs;
   HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
   HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-  g.events_used = 0;
-  const int rc = enqueue(cs, (const TaskDesc*)gr.tasks.p, (int*)gr.flow.p, true);
-  gr.n_events = g.events_used;
+  const size_t direct_events = g.events_used;   // the direct run's launches stay the last call's timing
+  const int rc = enqueue(cs, (const TaskDesc*)gr.tasks.p, (int*)gr.flow.p, false);
+  g.events_used = direct_events;
   hipGraph_t graph = nullptr;
   const hipError_t ec = hipStreamEndCapture(cs, &graph);
   (void)hipStreamDestroy(cs);

@@ -122,6 +122,7 @@ def test_graph_replay_matches_direct_run(rs, mode):
     n_ops = len(rs.plan(M, "hier", 3, "lf")[0])
     out = dict(phi0=torch.empty_like(ref[0]), u_pair=torch.empty_like(ref[1]),
                iters=torch.empty_like(ref[2]), status=torch.empty_like(ref[3]))
+    n_levels = rs.plan(M, "hier", 3, "lf")[1]
     for rep in range(4):
         for t in out.values():
             t.fill_(-7)                      # eager work between replays
@@ -129,6 +130,13 @@ def test_graph_replay_matches_direct_run(rs, mode):
         torch.cuda.synchronize()
         for want, got in zip(ref, (out["phi0"], out["u_pair"], out["iters"], out["status"])):
             assert torch.equal(want, got), rep
+        # timing probe: the capturing call reports its direct launches, a
+        # replay one duration for the whole graph, fresh on every replay
+        ms = rs.last_solve_launch_ms()
+        if rep == 0:
+            assert len(ms) == (1 if mode == "dataflow" else 1 + n_levels)
+        else:
+            assert len(ms) == 1 and ms[0] > 0.0
     assert out["iters"].shape[0] == M + n_ops
 
 
@@ -149,8 +157,8 @@ def _reg(args):
 def test_full_size_series256_sampled_prefixes(rs):
     """256 frames of 256x256, 2 levels, hierarchical plan (chunks of 4,
     Ladner-Fischer global phase) in the benchmark's launch configuration
-    (dataflow, replayed from a hipGraph: the first call captures, the second
-    replays), which must equal the level-synchronous run bitwise.  The oracle
+    (dataflow, direct launch), which must equal the level-synchronous run and
+    a graph capture and replay of the dataflow run bitwise.  The oracle
     recomputes, in the plan's combination order, the prefixes phi_{0,1..6} of
     the first chunk, and the independent pairwise registrations u_{k-1,k} for
     a sample of k across the series."""
@@ -168,10 +176,10 @@ def test_full_size_series256_sampled_prefixes(rs):
         M = frames.shape[0] - 1
         out = dict(phi0=torch.empty_like(lvl[0]), u_pair=torch.empty_like(lvl[1]),
                    iters=torch.empty_like(lvl[2]), status=torch.empty_like(lvl[3]))
-        for rep in range(2):
+        for rep, graph in enumerate((False, True, True)):
             for t in out.values():
                 t.fill_(-7)
-            rs.scan_run(fr, p, cfg.algo, cfg.chunk, cfg.global_algo, mode="dataflow", graph=True, out=out)
+            rs.scan_run(fr, p, cfg.algo, cfg.chunk, cfg.global_algo, mode="dataflow", graph=graph, out=out)
             torch.cuda.synchronize()
             for want, got in zip(lvl, (out["phi0"], out["u_pair"], out["iters"], out["status"])):
                 assert torch.equal(want, got), rep
