@@ -138,16 +138,35 @@ __device__ __forceinline__ double bilin_value_shared(const SharedBuf& img, int H
          wy * (ox * (double)img.f32(yb * W + xa) + wx * (double)img.f32(yb * W + xb));
 }
 
-// Butterfly sum over the 64 lanes of a wavefront: every lane ends with the
-// same, order-fixed total.
+// A double moved across lanes by one DPP pattern (both halves); lanes with
+// no source, or outside the row / bank masks, receive 0.
+template <int CTRL, int ROW, int BANK>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, ROW, BANK, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, ROW, BANK, true);
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+
+// Order-fixed sum over the 64 lanes of a wavefront, returned to every lane:
+// a prefix tree inside each 16-lane row (row_shr 1, 2, 4, 8), then the rows
+// through row_bcast 15 and 31, the total ending in lane 63.  DPP moves stay
+// in the VALU (no LDS round trip per step).
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, kWave);
-  return v;
+  v += dpp_f64<0x111, 0xf, 0xf>(v);   // row_shr:1
+  v += dpp_f64<0x112, 0xf, 0xf>(v);   // row_shr:2
+  v += dpp_f64<0x114, 0xf, 0xe>(v);   // row_shr:4, banks 1-3
+  v += dpp_f64<0x118, 0xf, 0xc>(v);   // row_shr:8, banks 2-3
+  v += dpp_f64<0x142, 0xa, 0xf>(v);   // row_bcast:15 into rows 1 and 3
+  v += dpp_f64<0x143, 0xc, 0xf>(v);   // row_bcast:31 into rows 2 and 3
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = __builtin_amdgcn_readlane((unsigned)b, 63);
+  const unsigned hi = __builtin_amdgcn_readlane((unsigned)(b >> 32), 63);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 
 // Canonical order-fixed sum of n doubles by one wavefront: lane l adds
-// p[l], p[l+64], ... in sequence, then the butterfly.  Used for every
+// p[l], p[l+64], ... in sequence, then wave_sum.  Used for every
 // per-tile energy total so that all execution paths agree bitwise.
 __device__ __forceinline__ double wave_sum_array(const double* p, int n, int lane) {
   const SharedBuf buf(p);

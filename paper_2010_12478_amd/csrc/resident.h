@@ -26,7 +26,7 @@
 //
 // Per pixel and iteration the arithmetic is pixel_eval and gd_update, the tile
 // energy is summed in the order of the streaming sweep with the same tile
-// height (per lane over its rows, the butterfly, the 4 wavefronts), so both
+// height (per lane over its rows, wave_sum, the 4 wavefronts), so both
 // paths produce bitwise identical fields, energies and iteration counts.
 #pragma once
 

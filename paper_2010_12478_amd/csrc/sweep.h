@@ -128,7 +128,7 @@ struct Unit {
 // Sweeps the tiles first, first + stride, ... of level L (all of them for
 // stride 1 and first 0 is not implied: pass the workgroup's own share).  For
 // every tile the energy (and with GNORM the squared gradient norm) is summed
-// in a fixed order: per lane over its rows in order, the butterfly over the
+// in a fixed order: per lane over its rows in order, wave_sum over the
 // wavefront, then the 4 wavefronts in order; thread 0 stores it to
 // part[tile] (gpart[tile]).  Must be called by all kWG threads.
 //
