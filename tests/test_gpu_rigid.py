@@ -228,3 +228,43 @@ def test_full_size_series_sampled(rs, mode):
     err = np.abs(phi0 - truth)
     print(f"rigid full-size: max |dG| vs known motion {err[:, 1:].max():.3f} px, "
           f"max |d alpha| r {err[:, 0].max() * np.sqrt(orig.radius2(256, 256)):.3f} px")
+
+
+def test_large_series_sampled(rs):
+    """1024 frames of 512x512 (GPU-generated), 3 levels, hierarchical plan
+    with chunks of 32: the dataflow scan in one launch, sampled pairwise and
+    prefix registrations recomputed by the oracle from the GPU's inputs, and
+    the level-synchronous run agreeing with it."""
+    announce("rigid 1024 x 512x512 L=3")
+    cfg = get_config(3)
+    spec = replace(cfg.series, extra_noise_frac=0.0)
+    S = rigid_series(spec, device="cuda")
+    p = SolverParams(levels=3, max_iter=200, tau=RIGID_TAU)
+    M = spec.n_frames - 1
+    phi0, pairs, iters, status = rs.scan_run_rigid(S.frames, p, "hier", 32, "lf", mode="dataflow")
+    b_phi0, _, b_iters, _ = rs.scan_run_rigid(S.frames, p, "hier", 32, "lf", mode="batched")
+    phi0, pairs, iters, status = host(phi0), host(pairs), host(iters), host(status)
+    assert np.isfinite(phi0).all() and ((status & 6) == 0).all()
+    assert _px_err(host(b_phi0), phi0, 512, 512) <= TOL_PX
+    ops, _ = plans.make_plan(M, "hier", 32, "lf")
+    fin = plans.final_nodes(ops, M)
+    prefix_of = {int(fin[k]): k for k in range(M)}
+    pyr = {}
+
+    def P(f):
+        if f not in pyr:
+            pyr[f] = pyramid(S.frames[f].double().cpu().numpy(), p.levels)
+        return pyr[f]
+
+    rng = np.random.default_rng(11)
+    for k in rng.choice(M, 3, replace=False):
+        want = orig.register(P(k), P(k + 1), None, p)
+        assert _px_err(pairs[k], want.theta, 512, 512) <= TOL_PX
+        assert iters[k].tolist() == want.iters
+    cand = [q for q, r in enumerate(ops) if int(r[2]) in prefix_of and int(r[3]) < M and int(r[1]) in prefix_of]
+    for q in rng.choice(cand, 3, replace=False):
+        r = ops[q]
+        j, e, k = prefix_of[int(r[2])], int(r[3]), prefix_of[int(r[1])]
+        want = orig.register(P(0), P(k + 1), orig.compose(phi0[j], pairs[e]), p)
+        assert _px_err(phi0[k], want.theta, 512, 512) <= TOL_PX
+        assert iters[M + q].tolist() == want.iters
