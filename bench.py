@@ -172,7 +172,13 @@ def cpu_baseline(cfg, frames_cpu, n_total_regs, sample):
     regs_per_s = sample / wall
     M = fr.shape[0] - 1
     t_full = n_total_regs / regs_per_s
-    return {"value": M / t_full, "unit": "frames/s", "cores": cores, "kind": "oracle",
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), None)
+    except OSError:
+        pass
+    return {"value": M / t_full, "unit": "frames/s", "cores": cores, "kind": "oracle", "cpu_model": model,
             "sample": (f"{sample} pairwise registrations (frames 0..{sample}) of the workload, "
                        f"on {cores} worker processes (one per host core), {wall:.1f} s wall; scaled to the "
                        f"workload's {n_total_regs} registrations assuming perfect packing"),
