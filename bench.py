@@ -52,6 +52,8 @@ def parse():
     ap.add_argument("--no-mock", action="store_true", help="skip the mock-operator scan microbenchmarks")
     ap.add_argument("--no-flex", action="store_true", help="skip the flexible-segment (Algorithm 1) scan")
     ap.add_argument("--no-rigid", action="store_true", help="skip the rigid NCC operator scan")
+    ap.add_argument("--no-seq-deviation", action="store_true",
+                    help="skip the report of the scan's deviation from the sequential recursion")
     ap.add_argument("--cpu-sample", type=int, default=0, help="registrations in the oracle sample")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 3 device-to-device copies of MIB MiB (calibrates the HBM byte counters)")
@@ -400,6 +402,18 @@ def main():
                              "phases_ms": {"pairwise": round(mean([l[0] for l in launch_b]), 3),
                                            "scan_levels": round(mean([sum(l[1:]) for l in launch_b]), 3)},
                              "mode": "one persistent launch for the pairwise phase and one per scan level"}
+
+    if not args.no_seq_deviation:
+        # the same series registered by the sequential recursion (one op per
+        # level), reported against the benchmark plan's prefixes: a report,
+        # not a bound (equally good matches of a non-convex energy differ)
+        seq = rs.scan_run(frames, p, "seq", 0, cfg.global_algo, mode="dataflow", want_pairs=False)
+        d = (out["phi0"] - seq[0]).abs()
+        per_frame = d.flatten(1).amax(dim=1)
+        result["deviation_from_sequential"] = {
+            "max_abs_px": round(float(d.max()), 4), "rms_px": round(float(d.pow(2).mean().sqrt()), 5),
+            "median_frame_max_abs_px": round(float(per_frame.median()), 4),
+            "frames_within_1e-3_px": int((per_frame <= 1e-3).sum()), "frames": M}
 
     if not args.no_flex:
         # the reduce-then-scan with flexible segment boundaries (Algorithm 1)
