@@ -4,6 +4,7 @@ oracle's plans bit for bit (no GPU needed)."""
 import ctypes
 import os
 import re
+import sys
 
 import numpy as np
 import pytest
@@ -100,3 +101,65 @@ def test_invalid_arguments_rejected_before_any_gpu_use(rs):
     assert lib.reg_set_tuning(6, 0, -1) == -1
     assert lib.reg_set_tuning(0, 129, -1) == -1
     assert lib.reg_set_tuning(0, 0, 2) == -1
+
+
+def test_rigid_arguments_rejected_before_any_gpu_use(rs):
+    lib = rs.lib
+    from paper_2010_12478_amd._lib import params_struct
+    from synth import RIGID_TAU
+    from synth.configs import SolverParams
+    p = params_struct(SolverParams(levels=2, tau=RIGID_TAU))
+    ref = (ctypes.c_int32 * 1)(0)
+    bad_idx = (ctypes.c_int32 * 1)(5)
+    out = ctypes.c_void_p(16)
+    # template index outside [0, N)
+    rc = lib.reg_rigid_solve_batch(ctypes.c_void_p(16), 2, 32, 32, ref, bad_idx, None, out, None, None, 1,
+                                   ctypes.byref(p), None)
+    assert rc == -1 and b"out of range" in lib.reg_last_error()
+    # 18x18 is not divisible by 2^(levels-1) = 4
+    p3 = params_struct(SolverParams(levels=3, tau=RIGID_TAU))
+    rc = lib.reg_rigid_solve_batch(ctypes.c_void_p(16), 2, 18, 18, ref, ref, None, out, None, None, 1,
+                                   ctypes.byref(p3), None)
+    assert rc == -1 and b"divisible" in lib.reg_last_error()
+    # theta aliasing theta0
+    rc = lib.reg_rigid_solve_batch(ctypes.c_void_p(16), 2, 32, 32, ref, ref, out, out, None, None, 1,
+                                   ctypes.byref(p), None)
+    assert rc == -1 and b"alias" in lib.reg_last_error()
+    # scan: a single frame, an unknown mode, an unknown algorithm
+    rc = lib.scan_run_rigid(ctypes.c_void_p(16), 1, 32, 32, ctypes.byref(p), 0, 0, 0, 1, out, None, None, None,
+                            None)
+    assert rc == -1
+    rc = lib.scan_run_rigid(ctypes.c_void_p(16), 4, 32, 32, ctypes.byref(p), 0, 0, 0, 0, out, None, None, None,
+                            None)
+    assert rc == -1 and b"mode" in lib.reg_last_error()
+    rc = lib.scan_run_rigid(ctypes.c_void_p(16), 4, 32, 32, ctypes.byref(p), 9, 0, 0, 1, out, None, None, None,
+                            None)
+    assert rc == -1 and b"algorithm" in lib.reg_last_error()
+
+
+def _bench():
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("_bench", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_bench_algorithmic_counts():
+    """The roofline's per-step counts from iteration counts: the rigid pixel
+    passes (t + 1 evaluations for a level stopped at t, max_iter when capped)
+    and the dense bytes for a hand-counted case."""
+    import numpy as np
+    b = _bench()
+    it = np.array([[3, 0], [200, 5]])          # two registrations, 2 levels, cap 200
+    assert b.rigid_passes(it, 8, 8, 2, 200) == (4 + 200) * 64 + (1 + 6) * 16
+    one = b.algorithmic_bytes(np.array([[2]]), 1, 4, 4, 1, 50)
+    two = b.algorithmic_bytes(np.array([[3]]), 1, 4, 4, 1, 50)
+    assert two - one == b.SWEEP_BYTES * 16      # one more kept update of a 4x4 field
