@@ -163,3 +163,26 @@ def test_bench_algorithmic_counts():
     one = b.algorithmic_bytes(np.array([[2]]), 1, 4, 4, 1, 50)
     two = b.algorithmic_bytes(np.array([[3]]), 1, 4, 4, 1, 50)
     assert two - one == b.SWEEP_BYTES * 16      # one more kept update of a 4x4 field
+
+
+def test_size_limits_rejected_before_any_gpu_use(rs):
+    """Largest accepted frame: 16384 px per side and 2^26 pixels; beyond that,
+    and for non-positive sizes or batches, every entry point fails on the host."""
+    lib = rs.lib
+    from paper_2010_12478_amd._lib import params_struct
+    from synth.configs import SolverParams
+    p = params_struct(SolverParams(levels=1))
+    ref = (ctypes.c_int32 * 1)(0)
+    out = ctypes.c_void_p(16)
+    for H, W in ((16385, 64), (64, 16385), (8192, 16384), (0, 64), (64, -1)):
+        rc = lib.reg_solve_batch(ctypes.c_void_p(16), 1, H, W, ref, ref, None, out, None, None, 1,
+                                 ctypes.byref(p), 1, None)
+        assert rc == -1, (H, W)
+        rc = lib.reg_rigid_solve_batch(ctypes.c_void_p(16), 1, H, W, ref, ref, None, out, None, None, 1,
+                                       ctypes.byref(p), None)
+        assert rc == -1, (H, W)
+        rc = lib.scan_run(ctypes.c_void_p(16), 4, H, W, ctypes.byref(p), 0, 0, 0, 1, 0, out, None, None, None, None)
+        assert rc == -1, (H, W)
+    rc = lib.reg_solve_batch(ctypes.c_void_p(16), 1, 64, 64, ref, ref, None, out, None, None, -1,
+                             ctypes.byref(p), 1, None)
+    assert rc == -1 and b"batch" in lib.reg_last_error()
