@@ -106,9 +106,10 @@ RIGID_FLOP_PER_PIXEL_PASS = 67
 PEAK_FP64_TFLOPS = 78.6
 
 
-def rigid_passes(iters, H, W, levels, max_iter):
-    """Pixel passes of the rigid solver: a level that stopped at iteration t
-    evaluated t + 1 times, a capped level max_iter times."""
+def pixel_passes(iters, H, W, levels, max_iter):
+    """Pixel passes of a solver (one energy-and-gradient evaluation of one
+    pixel): a level that stopped at iteration t evaluated t + 1 times, a
+    capped level max_iter times."""
     import numpy as np
     px = 0
     for l in range(levels):
@@ -154,37 +155,83 @@ def ci95(xs):
     return float(t.ppf(0.975, n - 1) * sd / math.sqrt(n))
 
 
-def cpu_baseline(cfg, frames_cpu, n_total_regs, sample):
-    """Oracle throughput on the host cores: `sample` pairwise registrations of
-    the workload spread over one worker process per core, scaled to frames/s
-    assuming the full workload's registrations pack perfectly onto the same
-    cores (which favours the oracle: the scan's dependencies are ignored)."""
+def host_cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            return next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), None)
+    except OSError:
+        return None
+
+
+def _timed_pool(fn, args, cores):
     import multiprocessing as mp
     from concurrent.futures import ProcessPoolExecutor
+    t0 = time.perf_counter()
+    with ProcessPoolExecutor(max_workers=cores, mp_context=mp.get_context("fork")) as ex:
+        res = list(ex.map(fn, args))
+    return res, time.perf_counter() - t0
 
+
+def cpu_baseline(cfg, frames_cpu, sample):
+    """Oracle throughput on the host cores: `sample` pairwise registrations of
+    the workload spread over one worker process per core, as pixel passes per
+    second (a pass: one energy-and-gradient evaluation of one pixel; a level
+    stopped at iteration t makes t + 1 passes, a capped level max_iter).
+    finish_cpu_baseline turns it into frames/s for the workload's pixel
+    passes, taken from the GPU run's iteration counts (the oracle's are the
+    same), assuming they pack perfectly onto the same cores (which favours the
+    oracle: the scan's dependencies are ignored)."""
+    import numpy as np
     cores = min(len(os.sched_getaffinity(0)), 16)
     sample = min(sample or 16 * cores, frames_cpu.shape[0] - 1)
     fr = frames_cpu.double().numpy()
     p = cfg.solver
-    args = [(fr[k - 1], fr[k], p) for k in range(1, sample + 1)]
-    t0 = time.perf_counter()
-    with ProcessPoolExecutor(max_workers=cores, mp_context=mp.get_context("fork")) as ex:
-        res = list(ex.map(_oracle_pair, args))
-    wall = time.perf_counter() - t0
-    regs_per_s = sample / wall
-    M = fr.shape[0] - 1
-    t_full = n_total_regs / regs_per_s
-    model = None
-    try:
-        with open("/proc/cpuinfo") as f:
-            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), None)
-    except OSError:
-        pass
-    return {"value": M / t_full, "unit": "frames/s", "cores": cores, "kind": "oracle", "cpu_model": model,
-            "sample": (f"{sample} pairwise registrations (frames 0..{sample}) of the workload, "
-                       f"on {cores} worker processes (one per host core), {wall:.1f} s wall; scaled to the "
-                       f"workload's {n_total_regs} registrations assuming perfect packing"),
-            "mean_iterations": float(sum(sum(r) for r in res) / len(res))}
+    H, W = fr.shape[1:]
+    res, wall = _timed_pool(_oracle_pair, [(fr[k - 1], fr[k], p) for k in range(1, sample + 1)], cores)
+    passes = pixel_passes(np.array(res), H, W, p.levels, p.max_iter)
+    return {"value": None, "unit": "frames/s", "cores": cores, "kind": "oracle", "cpu_model": host_cpu_model(),
+            "sample": (f"{sample} pairwise registrations (frames 0..{sample}) of the workload, on {cores} worker "
+                       f"processes (one per host core), {wall:.1f} s wall, {passes:.3g} pixel passes; scaled to "
+                       f"the workload's pixel passes assuming perfect packing"),
+            "pixel_passes_per_s": passes / wall,
+            "sample_mean_iterations_per_level": [round(float(x), 2) for x in np.array(res).mean(axis=0)]}
+
+
+def finish_cpu_baseline(base, M, workload_passes):
+    if base is not None:
+        base["value"] = M / (workload_passes / base["pixel_passes_per_s"])
+        base["workload_pixel_passes"] = int(workload_passes)
+    return base
+
+
+def rigid_cpu_baseline(cfg):
+    """The rigid operator's oracle on the host cores, as cpu_baseline: 8
+    pairwise registrations of the rigid series per core."""
+    import numpy as np
+    from dataclasses import replace
+
+    from synth import RIGID_TAU, rigid_series
+
+    cores = min(len(os.sched_getaffinity(0)), 16)
+    S = rigid_series(cfg.series)
+    fr = S.frames.double().numpy()
+    sample = min(8 * cores, fr.shape[0] - 1)
+    p = replace(cfg.solver, tau=RIGID_TAU)
+    H, W = fr.shape[1:]
+    res, wall = _timed_pool(_oracle_rigid_pair, [(fr[k - 1], fr[k], p) for k in range(1, sample + 1)], cores)
+    passes = pixel_passes(np.array(res), H, W, p.levels, p.max_iter)
+    return {"value": None, "unit": "frames/s", "cores": cores, "kind": "oracle",
+            "sample": (f"{sample} pairwise rigid registrations of the rigid series on {cores} worker processes, "
+                       f"{wall:.1f} s wall, {passes:.3g} pixel passes; scaled to the workload's pixel passes "
+                       f"assuming perfect packing"),
+            "pixel_passes_per_s": passes / wall}
+
+
+def _oracle_rigid_pair(a):
+    from oracle import rigid
+    from oracle.registration import pyramid
+    R, T, p = a
+    return rigid.register(pyramid(R, p.levels), pyramid(T, p.levels), None, p).iters
 
 
 def _oracle_pair(a):
@@ -257,7 +304,7 @@ def rigid_report(rs, cfg, steps):
     status = status.cpu().numpy()
     kms = mean([sum(k) for k in kern])
     n_launch = len(kern[0])
-    flop = RIGID_FLOP_PER_PIXEL_PASS * rigid_passes(iters, H, W, p.levels, p.max_iter)
+    flop = RIGID_FLOP_PER_PIXEL_PASS * pixel_passes(iters, H, W, p.levels, p.max_iter)
     achieved = flop / (kms / 1000.0) / 1e12
     err = np.abs(phi0.cpu().numpy() - S.theta[1:])
     r = math.sqrt(((W * W - 1) + (H * H - 1)) / 12.0)
@@ -315,7 +362,10 @@ def main():
 
     base = None
     if not args.no_cpu_baseline:
-        base = cpu_baseline(cfg, series.frames, n_regs, args.cpu_sample)   # before any GPU use
+        base = cpu_baseline(cfg, series.frames, args.cpu_sample)   # before any GPU use
+    rigid_base = None
+    if not args.no_cpu_baseline and not args.no_rigid:
+        rigid_base = rigid_cpu_baseline(cfg)                       # before any GPU use
 
     dev = torch.device("cuda:0")
     frames = series.frames.to(dev)
@@ -386,7 +436,7 @@ def main():
                      "kernel_ms_per_launch": round(kern_ms / max(1, kern_launches), 4),
                      "algorithmic_bytes_per_step": alg_step,
                      "algorithmic_bytes_per_launch": alg_step // max(1, kern_launches // max(1, args.steps))},
-        "cpu_baseline": base,
+        "cpu_baseline": finish_cpu_baseline(base, M, pixel_passes(iters, H, W, p.levels, p.max_iter)),
     }
 
     if not args.no_batched:
@@ -440,6 +490,8 @@ def main():
 
     if not args.no_rigid:
         result["rigid"] = rigid_report(rs, cfg, args.steps)
+        result["rigid"]["cpu_baseline"] = finish_cpu_baseline(
+            rigid_base, M, result["rigid"]["roofline"]["flop_per_step"] // RIGID_FLOP_PER_PIXEL_PASS)
 
     if not args.no_plain:
         torch.cuda.synchronize()

@@ -159,7 +159,7 @@ def test_bench_algorithmic_counts():
     import numpy as np
     b = _bench()
     it = np.array([[3, 0], [200, 5]])          # two registrations, 2 levels, cap 200
-    assert b.rigid_passes(it, 8, 8, 2, 200) == (4 + 200) * 64 + (1 + 6) * 16
+    assert b.pixel_passes(it, 8, 8, 2, 200) == (4 + 200) * 64 + (1 + 6) * 16
     one = b.algorithmic_bytes(np.array([[2]]), 1, 4, 4, 1, 50)
     two = b.algorithmic_bytes(np.array([[3]]), 1, 4, 4, 1, 50)
     assert two - one == b.SWEEP_BYTES * 16      # one more kept update of a 4x4 field
