@@ -728,7 +728,6 @@ __device__ int rigid_next(const RigidArgs& a, int* abort_flag) {
 // two at a time, so that a lone wavefront has independent work to issue.
 __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) k_rigid(RigidArgs a) {
   __shared__ double tacc[kRigidSums][kWG + 16];   // row padding: 2-way bank use on the strided reads
-  __shared__ double red[kRigidSums][17];
   __shared__ double s_sum[16];
   __shared__ int s_flag, s_task;
   const int xcd = blockIdx.x & 7, lb = blockIdx.x >> 3;
@@ -818,26 +817,24 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) k
             if (y < row1) rigid_pixel(rb, tb, pitch, w, h, x, y, cadx, sadx, ca, sa, cx, cy, th[1], th[2], acc);
           }
         }
-        // member partial sums through LDS: every thread's 14 sums, then 16
-        // threads per sum add 16 threads' values each (stride 16), then one
-        // thread per sum adds those 16 partials
+        // member partial sums through LDS: every thread's 14 sums, then the
+        // 16 lanes of one DPP row per sum add 16 threads' values each (stride
+        // 16) and the row's 16 partials (row_shr 1, 2, 4, 8: lane 15 holds
+        // the member's sum)
 #pragma unroll
         for (int j = 0; j < kRigidSums; ++j) tacc[j][threadIdx.x] = acc[j];
         __syncthreads();
-        if (threadIdx.x < kRigidSums * 16) {
+        double* pp = part + (size_t)par * a.g * 16;
+        if (threadIdx.x < kRigidSums * 16) {   // whole 16-lane rows
           const int j = threadIdx.x >> 4, q = threadIdx.x & 15;
           double v = 0.0;
 #pragma unroll
           for (int k = 0; k < kWG / 16; ++k) v += tacc[j][q + 16 * k];
-          red[j][q] = v;
-        }
-        __syncthreads();
-        double* pp = part + (size_t)par * a.g * 16;
-        if (threadIdx.x < kRigidSums) {
-          double v = 0.0;
-#pragma unroll
-          for (int q = 0; q < 16; ++q) v += red[threadIdx.x][q];
-          pp[G.member * 16 + threadIdx.x] = v;
+          v += dpp_f64<0x111, 0xf, 0xf>(v);
+          v += dpp_f64<0x112, 0xf, 0xf>(v);
+          v += dpp_f64<0x114, 0xf, 0xe>(v);
+          v += dpp_f64<0x118, 0xf, 0xc>(v);
+          if (q == 15) pp[G.member * 16 + j] = v;
         }
         if (!group_sync(G, abort_flag, a.spin_limit, &s_flag)) return;
         if (threadIdx.x < kRigidSums) {
