@@ -52,6 +52,7 @@ def parse():
     ap.add_argument("--no-mock", action="store_true", help="skip the mock-operator scan microbenchmarks")
     ap.add_argument("--no-flex", action="store_true", help="skip the flexible-segment (Algorithm 1) scan")
     ap.add_argument("--no-rigid", action="store_true", help="skip the rigid NCC operator scan")
+    ap.add_argument("--no-kernels", action="store_true", help="skip the standalone warp / energy kernel timings")
     ap.add_argument("--no-seq-deviation", action="store_true",
                     help="skip the report of the scan's deviation from the sequential recursion")
     ap.add_argument("--cpu-sample", type=int, default=0, help="registrations in the oracle sample")
@@ -325,6 +326,51 @@ def rigid_report(rs, cfg, steps):
                         "mode": "one persistent launch for the pairwise phase and one per scan level"}}
 
 
+def standalone_kernels(rs):
+    """The C ABI's standalone kernels on the autograd workload's shape (64
+    pairs of 512x512 float32, a smooth +-3 px displacement): mean duration over
+    10 calls from HIP events on the stream the library launches on, and the
+    achieved algorithmic bandwidth (warp 16 B/px: u 8 + T 4 + out 4;
+    energy and gradient 24 B/px: R 4 + T 4 + u 8 + gradient 8; energy only
+    16 B/px; adjoint 16 B/px: gout 4 + u 8 + the gathered tap values' scatter
+    counted as 4)."""
+    import torch
+    B, H, W = 64, 512, 512
+    g = torch.Generator(device="cuda")
+    g.manual_seed(3)
+    T = torch.rand((B, H, W), device="cuda", generator=g)
+    R = torch.rand((B, H, W), device="cuda", generator=g)
+    yy = torch.arange(H, device="cuda", dtype=torch.float32).view(1, H, 1)
+    xx = torch.arange(W, device="cuda", dtype=torch.float32).view(1, 1, W)
+    ph = torch.rand((B, 1, 1), device="cuda", generator=g) * 6.28
+    u = torch.stack([3.0 * torch.sin(2 * math.pi * yy / H + ph) + 0 * xx,
+                     3.0 * torch.sin(2 * math.pi * xx / W + ph) + 0 * yy], dim=1).contiguous()
+    out = torch.empty_like(T)
+    gT = torch.zeros_like(T)
+    px = B * H * W
+
+    def timeit(fn, reps=10):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    rows = {}
+    for name, fn, bpp in (("reg_warp", lambda: rs.warp(T, u, out), 16),
+                          ("reg_energy_grad", lambda: rs.energy_grad(R, T, u, 0.1, want_grad=True), 24),
+                          ("reg_energy_grad (energy only)", lambda: rs.energy_grad(R, T, u, 0.1, want_grad=False), 16),
+                          ("reg_warp_adjoint", lambda: rs.warp_adjoint(out, u, gT), 16)):
+        ms = timeit(fn)
+        gbs = bpp * px / (ms / 1000.0) / 1e9
+        rows[name] = {"ms": round(ms, 4), "GB/s": round(gbs, 1), "frac": round(gbs / PEAK_HBM_GBS, 4)}
+    return {"shape": "64 x 512x512 float32", "kernels": rows}
+
+
 def main():
     args = parse()
     if args.copy_probe:
@@ -503,6 +549,8 @@ def main():
                            "ms_per_step": round(1000 * plain_s, 1),
                            "mode": "one registration at a time, one launch per iteration, host energy read-back"}
         result["batched_over_plain"] = round(value / (M / plain_s), 2)
+    if not args.no_kernels:
+        result["standalone_kernels"] = standalone_kernels(rs)
     if not args.no_mock:
         result["mock_scan"] = mock_scan_report(rs)
     result["input_generation_s"] = round(gen_s, 2)

@@ -11,6 +11,10 @@ import ctypes
 import os
 
 import numpy as np
+# torch's HIP runtime first: the library then binds to the runtime already in
+# the process (loaded the other way round, two runtimes end up in one process
+# and the library finds no device)
+import torch  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libregscan.so")

@@ -68,6 +68,13 @@ __device__ __forceinline__ void bilin(const S* __restrict__ img, int H, int W, i
   dsy = ox * (i10 - i00) + wx * (i11 - i01);
 }
 
+// Bilinear value from the four taps (the order of bilin_value).
+__device__ __forceinline__ double bilin_taps(double i00, double i01, double i10, double i11, double wx, double wy) {
+#pragma clang fp contract(off)
+  const double ox = 1.0 - wx, oy = 1.0 - wy;
+  return oy * (ox * i00 + wx * i01) + wy * (ox * i10 + wx * i11);
+}
+
 template <typename S>
 __device__ __forceinline__ double bilin_value(const S* __restrict__ img, int H, int W, int x0, int y0,
                                               double wx, double wy) {
@@ -137,6 +144,28 @@ __device__ __forceinline__ double bilin_value_shared(const SharedBuf& img, int H
   return oy * (ox * (double)img.f32(ya * W + xa) + wx * (double)img.f32(ya * W + xb)) +
          wy * (ox * (double)img.f32(yb * W + xa) + wx * (double)img.f32(yb * W + xb));
 }
+
+// Whole-wavefront shift by one lane (DPP wave_shr:1 / wave_shl:1): lane i
+// receives v from lane i - 1 (from_left) or i + 1 (from_right); the lane
+// without a source (0, respectively 63) keeps its own `edge`.
+template <int CTRL>
+__device__ __forceinline__ float wave_shift(float v, float edge) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, edge),
+                                                               __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double wave_shift(double v, double edge) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const unsigned long long e = __builtin_bit_cast(unsigned long long, edge);
+  const int lo = __builtin_amdgcn_update_dpp((int)(unsigned)e, (int)(unsigned)b, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(unsigned)(e >> 32), (int)(unsigned)(b >> 32), CTRL, 0xf, 0xf,
+                                             false);
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned)lo);
+}
+template <typename S>
+__device__ __forceinline__ S wave_from_left(S v, S edge) { return wave_shift<0x138>(v, edge); }
+template <typename S>
+__device__ __forceinline__ S wave_from_right(S v, S edge) { return wave_shift<0x130>(v, edge); }
 
 // A double moved across lanes by one DPP pattern (both halves); lanes with
 // no source, or outside the row / bank masks, receive 0.

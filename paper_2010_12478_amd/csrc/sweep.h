@@ -115,14 +115,14 @@ __device__ __forceinline__ S gd_update(double c, double g, double tau) {
   return (S)(c - tau * g);
 }
 
-// Registers of one unit of work of a wavefront: rows [yb, ye) (at most kRB)
+// Registers of one unit of work of a wavefront: rows [yb, ye) (at most RB)
 // of one tile, lane = column.
-template <typename S>
+template <typename S, int RB>
 struct Unit {
   int tile, yb, ye;
-  S ax[kRB + 2], ay[kRB + 2];   // u at rows yb-1 .. yb+kRB of this lane's column (rows clamped)
-  S rr[kRB];                     // R at rows yb .. yb+kRB-1
-  S hx[kRB], hy[kRB];            // lane 0: u at column x-1, lane 63: u at column x+1
+  S ax[RB + 2], ay[RB + 2];   // u at rows yb-1 .. yb+RB of this lane's column (rows clamped)
+  S rr[RB];                     // R at rows yb .. yb+RB-1
+  S hx[RB], hy[RB];            // lane 0: u at column x-1, lane 63: u at column x+1
 };
 
 // Sweeps the tiles first, first + stride, ... of level L (all of them for
@@ -138,7 +138,7 @@ struct Unit {
 // and halo loads of unit i + 1, and unit i is computed while those are in
 // flight, so each unit exposes one memory round trip instead of two.
 // Arithmetic is double; the stored type S is float (or double).
-template <typename S, int WRITE, bool GNORM, bool PAD>
+template <typename S, int WRITE, bool GNORM, bool PAD, int RB = kRB>
 __device__ void sweep_tiles(const LevelView<S>& L, int first, int stride, int th, double* red, double* part,
                             double* gpart) {
   const int h = L.h, w = L.w;
@@ -146,7 +146,7 @@ __device__ void sweep_tiles(const LevelView<S>& L, int first, int stride, int th
   const int nt = tiles_of(h, w, th);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int rpw = th >> 2;
-  const int upt = (rpw + kRB - 1) / kRB;            // units per tile and wavefront
+  const int upt = (rpw + RB - 1) / RB;            // units per tile and wavefront
   const int my_tiles = first < nt ? (nt - first + stride - 1) / stride : 0;
   const int n_units = my_tiles * upt;
   const size_t hw = (size_t)h * w;
@@ -157,21 +157,21 @@ __device__ void sweep_tiles(const LevelView<S>& L, int first, int stride, int th
   const ReadBuf rb(L.R), tb(PAD ? L.T - pitch - 1 : L.T);
   const double lam = L.lam, tau = L.tau;
 
-  auto setup = [&](int i, Unit<S>& U) {
+  auto setup = [&](int i, Unit<S, RB>& U) {
     const int k = i / upt, b = i - k * upt;
     U.tile = first + k * stride;
     const int ty = U.tile / ntx;
     const int ys = ty * th + wave * rpw;
     const int yend = min(ys + rpw, h);
-    U.yb = ys + b * kRB;
-    U.ye = min(U.yb + kRB, yend);
+    U.yb = ys + b * RB;
+    U.ye = min(U.yb + RB, yend);
   };
-  auto load = [&](Unit<S>& U) {
+  auto load = [&](Unit<S, RB>& U) {
     if (U.yb >= U.ye) return;
     const int x = (U.tile % ntx) * kTileW + lane;
     const int xc = x < w ? x : w - 1;
 #pragma unroll
-    for (int r = 0; r < kRB + 2; ++r) {
+    for (int r = 0; r < RB + 2; ++r) {
       // rows clamped to the image: at the top / bottom edge the missing
       // neighbour row is the pixel's own row
       const int row = __mul24(clampi(U.yb - 1 + r, 0, h - 1), w);
@@ -179,13 +179,13 @@ __device__ void sweep_tiles(const LevelView<S>& L, int first, int stride, int th
       U.ay[r] = ub.load<S>(ihw + row + xc);
     }
 #pragma unroll
-    for (int r = 0; r < kRB; ++r) U.rr[r] = rb.load<S>(__mul24(min(U.yb + r, h - 1), pitch) + xc);
+    for (int r = 0; r < RB; ++r) U.rr[r] = rb.load<S>(__mul24(min(U.yb + r, h - 1), pitch) + xc);
     if (lane == 0 || lane == kWave - 1) {
       // the column outside the tile, clamped to the image: at the image edge
       // it is the pixel's own column, so the missing difference is exactly 0
       const int xn = clampi(lane == 0 ? x - 1 : x + 1, 0, w - 1);
 #pragma unroll
-      for (int r = 0; r < kRB; ++r) {
+      for (int r = 0; r < RB; ++r) {
         const int row = __mul24(min(U.yb + r, h - 1), w);
         U.hx[r] = ub.load<S>(row + xn);
         U.hy[r] = ub.load<S>(ihw + row + xn);
@@ -193,7 +193,7 @@ __device__ void sweep_tiles(const LevelView<S>& L, int first, int stride, int th
     }
   };
 
-  Unit<S> A, B;
+  Unit<S, RB> A, B;
   double accR = 0.0, accG = 0.0, accN = 0.0;
   if (n_units > 0) {
     setup(0, A);
@@ -204,11 +204,11 @@ __device__ void sweep_tiles(const LevelView<S>& L, int first, int stride, int th
     const bool vx = x < w;
     const int xc = vx ? x : w - 1;
     // gathers of T for this unit
-    S taps[kRB][4];
-    float flx[kRB], fly[kRB];  // float32 floors of the displacement (the cells)
+    S taps[RB][4];
+    float flx[RB], fly[RB];  // float32 floors of the displacement (the cells)
     if (A.yb < A.ye) {
 #pragma unroll
-      for (int r = 0; r < kRB; ++r) {
+      for (int r = 0; r < RB; ++r) {
         int ix, iy;
         flx[r] = floor_cell((float)A.ax[r + 1], ix);
         fly[r] = floor_cell((float)A.ay[r + 1], iy);
@@ -237,23 +237,17 @@ __device__ void sweep_tiles(const LevelView<S>& L, int first, int stride, int th
     }
     if (A.yb < A.ye) {
 #pragma unroll
-      for (int r = 0; r < kRB; ++r) {
+      for (int r = 0; r < RB; ++r) {
         const int y = A.yb + r;
         if (y >= A.ye) break;
         const S cxs = A.ax[r + 1], cys = A.ay[r + 1];
         // neighbours: lanes past the right edge hold column w - 1, so every
         // missing neighbour equals the pixel's own value (difference +0.0,
         // the same as leaving the term out)
-        S lxs = __shfl_up(cxs, 1, kWave), lys = __shfl_up(cys, 1, kWave);
-        S rxs = __shfl_down(cxs, 1, kWave), rys = __shfl_down(cys, 1, kWave);
-        if (lane == 0) {
-          lxs = A.hx[r];
-          lys = A.hy[r];
-        }
-        if (lane == kWave - 1) {
-          rxs = A.hx[r];
-          rys = A.hy[r];
-        }
+        // lane 0 holds the column left of the tile in hx/hy, lane 63 the one
+        // right of it
+        const S lxs = wave_from_left(cxs, A.hx[r]), lys = wave_from_left(cys, A.hy[r]);
+        const S rxs = wave_from_right(cxs, A.hx[r]), rys = wave_from_right(cys, A.hy[r]);
         const double cx = cxs, cy = cys;
         double nR = accR, nG = accG, gx, gy;   // accumulated only for pixels inside the grid
         pixel_eval(cx - (double)flx[r], cy - (double)fly[r], taps[r][0], taps[r][1], taps[r][2], taps[r][3],
