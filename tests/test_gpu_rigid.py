@@ -268,3 +268,39 @@ def test_large_series_sampled(rs):
         want = orig.register(P(0), P(k + 1), orig.compose(phi0[j], pairs[e]), p)
         assert _px_err(phi0[k], want.theta, 512, 512) <= TOL_PX
         assert iters[M + q].tolist() == want.iters
+
+
+def test_paper_scale_series_sampled(rs):
+    """4096 frames of 1024x1024 (GPU-generated), 4 levels, hierarchical plan
+    with chunks of 64, dataflow: every output finite, sampled pairwise and
+    prefix registrations recomputed by the oracle from the GPU's inputs."""
+    announce("rigid 4096 x 1024x1024 L=4")
+    cfg = get_config(5)
+    S = rigid_series(cfg.series, device="cuda")
+    p = SolverParams(levels=4, max_iter=200, tau=RIGID_TAU)
+    M = cfg.series.n_frames - 1
+    phi0, pairs, iters, status = rs.scan_run_rigid(S.frames, p, "hier", 64, "lf", mode="dataflow")
+    phi0, pairs, iters, status = host(phi0), host(pairs), host(iters), host(status)
+    assert np.isfinite(phi0).all() and ((status & 6) == 0).all()
+    ops, _ = plans.make_plan(M, "hier", 64, "lf")
+    fin = plans.final_nodes(ops, M)
+    prefix_of = {int(fin[k]): k for k in range(M)}
+    pyr = {}
+
+    def P(f):
+        if f not in pyr:
+            pyr[f] = pyramid(S.frames[f].double().cpu().numpy(), p.levels)
+        return pyr[f]
+
+    rng = np.random.default_rng(13)
+    for k in rng.choice(M, 2, replace=False):
+        want = orig.register(P(k), P(k + 1), None, p)
+        assert _px_err(pairs[k], want.theta, 1024, 1024) <= TOL_PX
+        assert iters[k].tolist() == want.iters
+    cand = [q for q, r in enumerate(ops) if int(r[2]) in prefix_of and int(r[3]) < M and int(r[1]) in prefix_of]
+    for q in rng.choice(cand, 2, replace=False):
+        r = ops[q]
+        j, e, k = prefix_of[int(r[2])], int(r[3]), prefix_of[int(r[1])]
+        want = orig.register(P(0), P(k + 1), orig.compose(phi0[j], pairs[e]), p)
+        assert _px_err(phi0[k], want.theta, 1024, 1024) <= TOL_PX
+        assert iters[M + q].tolist() == want.iters
