@@ -333,7 +333,8 @@ def standalone_kernels(rs):
     achieved algorithmic bandwidth (warp 16 B/px: u 8 + T 4 + out 4;
     energy and gradient 24 B/px: R 4 + T 4 + u 8 + gradient 8; energy only
     16 B/px; adjoint 16 B/px: gout 4 + u 8 + the gathered tap values' scatter
-    counted as 4)."""
+    counted as 4; backward of the one-level energy 32 B/px: Ia 4 gathered +
+    u 8 + Ib 4 read, du 8 + dIb 4 written, dIa 4 scattered)."""
     import torch
     B, H, W = 64, 512, 512
     g = torch.Generator(device="cuda")
@@ -347,6 +348,7 @@ def standalone_kernels(rs):
                      3.0 * torch.sin(2 * math.pi * xx / W + ph) + 0 * yy], dim=1).contiguous()
     out = torch.empty_like(T)
     gT = torch.zeros_like(T)
+    gE = torch.ones(B, dtype=torch.float64, device="cuda")
     px = B * H * W
 
     def timeit(fn, reps=10):
@@ -364,7 +366,9 @@ def standalone_kernels(rs):
     for name, fn, bpp in (("reg_warp", lambda: rs.warp(T, u, out), 16),
                           ("reg_energy_grad", lambda: rs.energy_grad(R, T, u, 0.1, want_grad=True), 24),
                           ("reg_energy_grad (energy only)", lambda: rs.energy_grad(R, T, u, 0.1, want_grad=False), 16),
-                          ("reg_warp_adjoint", lambda: rs.warp_adjoint(out, u, gT), 16)):
+                          ("reg_warp_adjoint", lambda: rs.warp_adjoint(out, u, gT), 16),
+                          ("reg_pyramid_energy_backward (1 level)",
+                           lambda: rs.pyramid_energy_backward(T, u, R, 0.1, 1, gE), 32)):
         ms = timeit(fn)
         gbs = bpp * px / (ms / 1000.0) / 1e9
         rows[name] = {"ms": round(ms, 4), "GB/s": round(gbs, 1), "frac": round(gbs / PEAK_HBM_GBS, 4)}

@@ -154,6 +154,10 @@ __device__ __forceinline__ float wave_shift(float v, float edge) {
                                                                __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
 }
 template <int CTRL>
+__device__ __forceinline__ int wave_shift(int v, int edge) {
+  return __builtin_amdgcn_update_dpp(edge, v, CTRL, 0xf, 0xf, false);
+}
+template <int CTRL>
 __device__ __forceinline__ double wave_shift(double v, double edge) {
   const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
   const unsigned long long e = __builtin_bit_cast(unsigned long long, edge);

@@ -142,34 +142,124 @@ __global__ void __launch_bounds__(kEW) k_warp(const S* __restrict__ T, const S* 
 __device__ __forceinline__ void atomic_add(float* p, float v) { unsafeAtomicAdd(p, v); }
 __device__ __forceinline__ void atomic_add(double* p, double v) { unsafeAtomicAdd(p, v); }
 
-// Scatter v(x) into the four clamped taps of x + u(x) with bilinear weights.
+// Scatters of the adjoint kernels.  A thread takes kAdjRows consecutive rows
+// of one column; the bilinear shares of a pixel go to two upper taps (row
+// ya) and two lower taps (row yb).  Shares that land on one cell are added
+// in registers before the single atomic addition that carries them:
+//  - rows: the lower taps of row y are held back and joined to the upper
+//    taps of row y + 1 when those are the same two cells (the common case of
+//    a smooth field); otherwise they are added to the destination;
+//  - columns: a lane adds its left neighbour's right share into its own left
+//    share when both are the same cell, and the neighbour then leaves it out.
+// On smooth fields that leaves about one full-wavefront atomic per row of
+// pixels instead of four.  The order of the additions is not fixed (as with
+// any atomic sum).
+constexpr int kAdjRows = 8;
+
 template <typename S>
-__device__ __forceinline__ void scatter_taps(S* __restrict__ gT, int H, int W, int x, int y, S ux, S uy, double v) {
-  int ix, iy;
-  double fx, fy;
-  cell_of(ux, ix, fx);
-  cell_of(uy, iy, fy);
-  const int x0 = x + ix, y0 = y + iy;
-  const int xa = clampi(x0, 0, W - 1), xb = clampi(x0 + 1, 0, W - 1);
-  const int ya = clampi(y0, 0, H - 1), yb = clampi(y0 + 1, 0, H - 1);
-  const double ox = 1.0 - fx, oy = 1.0 - fy;
-  atomic_add(gT + ya * W + xa, (S)(v * ox * oy));
-  atomic_add(gT + ya * W + xb, (S)(v * fx * oy));
-  atomic_add(gT + yb * W + xa, (S)(v * ox * fy));
-  atomic_add(gT + yb * W + xb, (S)(v * fx * fy));
+struct TapPair {   // two horizontally adjacent taps of one row; y < 0: none
+  int y, xa, xb;
+  S va, vb;
+};
+
+template <typename S>
+__device__ __forceinline__ TapPair<S> no_taps() {
+  TapPair<S> t;
+  t.y = t.xa = t.xb = -1;
+  t.va = t.vb = S(0);
+  return t;
 }
 
+// Adds every lane's pair to dst (row pitch W).  Called by all lanes of the
+// wavefront together (the column join reads the neighbours' registers).
+template <typename S>
+__device__ __forceinline__ void emit_taps(S* __restrict__ dst, int W, TapPair<S> t) {
+  const int ly = wave_shift<0x138>(t.y, -1), lxb = wave_shift<0x138>(t.xb, -1);
+  const S lvb = wave_from_left(t.vb, S(0));
+  const bool take = t.y >= 0 && ly == t.y && lxb == t.xa;
+  if (take) t.va += lvb;
+  const int given = wave_shift<0x130>((int)take, 0);
+  if (t.y >= 0) {
+    atomic_add(dst + t.y * W + t.xa, t.va);
+    if (!given) atomic_add(dst + t.y * W + t.xb, t.vb);
+  }
+}
+
+// The row-by-row scatter of one thread's column (see above).
+template <typename S>
+struct RowScatter {
+  TapPair<S> low = no_taps<S>();   // lower taps held back from the previous row
+
+  // v(x, y) into the four clamped taps of (x, y) + (ux, uy) with bilinear
+  // weights; a lane without a pixel (valid false) still takes part
+  __device__ __forceinline__ void pixel(S* __restrict__ dst, int H, int W, bool valid, int x, int y, S ux, S uy,
+                                        double v) {
+    TapPair<S> up = no_taps<S>(), lo = no_taps<S>();
+    if (valid) {
+      int ix, iy;
+      double fx, fy;
+      cell_of(ux, ix, fx);
+      cell_of(uy, iy, fy);
+      const int xa = clampi(x + ix, 0, W - 1), xb = clampi(x + ix + 1, 0, W - 1);
+      const double ox = 1.0 - fx, oy = 1.0 - fy;
+      up.y = clampi(y + iy, 0, H - 1);
+      lo.y = clampi(y + iy + 1, 0, H - 1);
+      up.xa = lo.xa = xa;
+      up.xb = lo.xb = xb;
+      up.va = (S)(v * ox * oy);
+      up.vb = (S)(v * fx * oy);
+      lo.va = (S)(v * ox * fy);
+      lo.vb = (S)(v * fx * fy);
+    }
+    const bool join = low.y >= 0 && up.y == low.y && up.xa == low.xa && up.xb == low.xb;
+    if (join) {
+      up.va += low.va;
+      up.vb += low.vb;
+    }
+    emit_taps(dst, W, join ? no_taps<S>() : low);
+    emit_taps(dst, W, up);
+    low = lo;
+  }
+  __device__ __forceinline__ void finish(S* __restrict__ dst, int W) {
+    emit_taps(dst, W, low);
+    low = no_taps<S>();
+  }
+};
+
+// Grid of the adjoint kernels: column blocks x (item, group of kAdjRows rows),
+// at most 65535 groups (grid-strided beyond).
+inline dim3 adjoint_grid(int B, int H, int W) {
+  const long long groups = (long long)B * ((H + kAdjRows - 1) / kAdjRows);
+  return dim3((unsigned)((W + kEW - 1) / kEW), (unsigned)(groups < 65535 ? groups : 65535));
+}
+
+// gT[b] += adjoint of the warp of item b applied to g[b] (grid: adjoint_grid)
 template <typename S>
 __global__ void __launch_bounds__(kEW) k_warp_adjoint(const S* __restrict__ g, const S* __restrict__ u,
                                                       S* __restrict__ gT, int B, int H, int W) {
   const size_t HW = (size_t)H * W;
   const int x = blockIdx.x * kEW + threadIdx.x;
-  if (x >= W) return;
-  for (int row = blockIdx.y; row < B * H; row += gridDim.y) {
-    const int b = row / H, y = row - b * H;   // wave-uniform
-    const size_t r = (size_t)y * W + x;
+  const bool col = x < W;
+  const int xl = col ? x : W - 1;   // loads of lanes past the last column: any pixel
+  const int gpi = (H + kAdjRows - 1) / kAdjRows;
+  for (long long t = blockIdx.y; t < (long long)B * gpi; t += gridDim.y) {   // wave-uniform
+    const int b = (int)(t / gpi), y0 = (int)(t - (long long)b * gpi) * kAdjRows;
     const S* ub = u + (size_t)b * 2 * HW;
-    scatter_taps(gT + (size_t)b * HW, H, W, x, y, ub[r], ub[HW + r], (double)g[(size_t)b * HW + r]);
+    const S* gb = g + (size_t)b * HW;
+    S vx[kAdjRows], vy[kAdjRows], vg[kAdjRows];
+#pragma unroll
+    for (int k = 0; k < kAdjRows; ++k) {
+      const int r = min(y0 + k, H - 1) * W + xl;
+      vx[k] = ub[r];
+      vy[k] = ub[HW + r];
+      vg[k] = gb[r];
+    }
+    RowScatter<S> sc;
+    S* tb = gT + (size_t)b * HW;
+#pragma unroll
+    for (int k = 0; k < kAdjRows; ++k)
+      sc.pixel(tb, H, W, col && y0 + k < H, x, y0 + k, vx[k], vy[k], (double)vg[k]);
+    sc.finish(tb, W);
   }
 }
 
@@ -221,43 +311,64 @@ __global__ void __launch_bounds__(kEW) k_energy_backward(const S* __restrict__ I
                                                          const double* __restrict__ gE, S* dIa, S* du,
                                                          S* dIb, const S* du_c, const S* dIb_c,
                                                          int B, int H, int W) {
-  const size_t HW = (size_t)H * W, n = (size_t)B * HW;
+  const size_t HW = (size_t)H * W;
   const int hc = H >> 1, wc = W >> 1;
   const size_t HWc = (size_t)hc * wc;
-  for (size_t t = blockIdx.x * (size_t)kEW + threadIdx.x; t < n; t += (size_t)gridDim.x * kEW) {
-    const size_t b = t / HW;
-    const int r = (int)(t - b * HW);
-    const int y = r / W, x = r - y * W;
-    const S* ux = u + b * 2 * HW;
+  const int x = blockIdx.x * kEW + threadIdx.x;
+  const bool col = x < W;
+  const int gpi = (H + kAdjRows - 1) / kAdjRows;
+  for (long long t = blockIdx.y; t < (long long)B * gpi; t += gridDim.y) {   // wave-uniform
+    const int b = (int)(t / gpi), y0 = (int)(t - (long long)b * gpi) * kAdjRows;
+    const S* ux = u + (size_t)b * 2 * HW;
     const S* uy = ux + HW;
-    const S cxs = ux[r], cys = uy[r];
-    int ix, iy;
-    double fx, fy;
-    cell_of(cxs, ix, fx);
-    cell_of(cys, iy, fy);
-    double s, dsx, dsy;
-    bilin(Ia + b * HW, H, W, x + ix, y + iy, fx, fy, s, dsx, dsy);
-    const double res = s - (double)Ib[t];
-    const double cx = cxs, cy = cys;
-    double nbx = 0.0, nby = 0.0;
-    if (x > 0) { nbx += cx - (double)ux[r - 1]; nby += cy - (double)uy[r - 1]; }
-    if (x + 1 < W) { nbx += cx - (double)ux[r + 1]; nby += cy - (double)uy[r + 1]; }
-    if (y > 0) { nbx += cx - (double)ux[r - W]; nby += cy - (double)uy[r - W]; }
-    if (y + 1 < H) { nbx += cx - (double)ux[r + W]; nby += cy - (double)uy[r + W]; }
     const double w = gE[b];
-    double gx = w * (2.0 * res * dsx + 2.0 * lam * nbx);
-    double gy = w * (2.0 * res * dsy + 2.0 * lam * nby);
-    double gb = w * (-2.0 * res);
-    if (du_c) {
-      const size_t pc = b * 2 * HWc + (size_t)(y >> 1) * wc + (x >> 1);
-      gx += 0.125 * (double)du_c[pc];
-      gy += 0.125 * (double)du_c[pc + HWc];
+    // the rows' outputs du and dIb first (their loads free to overlap: the
+    // inputs are restrict), the scatters of dIa after them
+    S sx[kAdjRows], sy[kAdjRows];
+    double sv[kAdjRows];
+#pragma unroll
+    for (int k = 0; k < kAdjRows; ++k) {
+      sx[k] = sy[k] = S(0);
+      sv[k] = 0.0;
+      const int y = y0 + k;
+      if (!col || y >= H) continue;
+      const int r = y * W + x;
+      const size_t q = (size_t)b * HW + r;
+      const S cxs = ux[r], cys = uy[r];
+      int ix, iy;
+      double fx, fy;
+      cell_of(cxs, ix, fx);
+      cell_of(cys, iy, fy);
+      double s, dsx, dsy;
+      bilin(Ia + (size_t)b * HW, H, W, x + ix, y + iy, fx, fy, s, dsx, dsy);
+      const double res = s - (double)Ib[q];
+      const double cx = cxs, cy = cys;
+      double nbx = 0.0, nby = 0.0;
+      if (x > 0) { nbx += cx - (double)ux[r - 1]; nby += cy - (double)uy[r - 1]; }
+      if (x + 1 < W) { nbx += cx - (double)ux[r + 1]; nby += cy - (double)uy[r + 1]; }
+      if (y > 0) { nbx += cx - (double)ux[r - W]; nby += cy - (double)uy[r - W]; }
+      if (y + 1 < H) { nbx += cx - (double)ux[r + W]; nby += cy - (double)uy[r + W]; }
+      double gx = w * (2.0 * res * dsx + 2.0 * lam * nbx);
+      double gy = w * (2.0 * res * dsy + 2.0 * lam * nby);
+      double gb = w * (-2.0 * res);
+      if (du_c) {
+        const size_t pc = (size_t)b * 2 * HWc + (size_t)(y >> 1) * wc + (x >> 1);
+        gx += 0.125 * (double)du_c[pc];
+        gy += 0.125 * (double)du_c[pc + HWc];
+      }
+      if (dIb_c) gb += 0.25 * (double)dIb_c[(size_t)b * HWc + (size_t)(y >> 1) * wc + (x >> 1)];
+      du[(size_t)b * 2 * HW + r] = (S)gx;
+      du[(size_t)b * 2 * HW + HW + r] = (S)gy;
+      dIb[q] = (S)gb;
+      sx[k] = cxs;
+      sy[k] = cys;
+      sv[k] = w * 2.0 * res;
     }
-    if (dIb_c) gb += 0.25 * (double)dIb_c[b * HWc + (size_t)(y >> 1) * wc + (x >> 1)];
-    du[b * 2 * HW + r] = (S)gx;
-    du[b * 2 * HW + HW + r] = (S)gy;
-    dIb[t] = (S)gb;
-    scatter_taps(dIa + b * HW, H, W, x, y, cxs, cys, w * 2.0 * res);
+    RowScatter<S> sc;
+    S* db = dIa + (size_t)b * HW;
+#pragma unroll
+    for (int k = 0; k < kAdjRows; ++k) sc.pixel(db, H, W, col && y0 + k < H, x, y0 + k, sx[k], sy[k], sv[k]);
+    sc.finish(db, W);
   }
 }
 
@@ -360,10 +471,10 @@ hipError_t launch_warp_adjoint(const void* g, const void* u, void* gT, int B, in
                                hipStream_t s) {
   if ((size_t)B * H * W == 0) return hipSuccess;
   if (f64)
-    hipLaunchKernelGGL(k_warp_adjoint<double>, row_grid(B, H, W), dim3(kEW), 0, s, (const double*)g,
+    hipLaunchKernelGGL(k_warp_adjoint<double>, adjoint_grid(B, H, W), dim3(kEW), 0, s, (const double*)g,
                        (const double*)u, (double*)gT, B, H, W);
   else
-    hipLaunchKernelGGL(k_warp_adjoint<float>, row_grid(B, H, W), dim3(kEW), 0, s, (const float*)g,
+    hipLaunchKernelGGL(k_warp_adjoint<float>, adjoint_grid(B, H, W), dim3(kEW), 0, s, (const float*)g,
                        (const float*)u, (float*)gT, B, H, W);
   return hipGetLastError();
 }
@@ -410,11 +521,11 @@ hipError_t launch_energy_backward_level(const void* Ia, const void* u, const voi
   const size_t n = (size_t)B * h * w;
   if (n == 0) return hipSuccess;
   if (f64)
-    hipLaunchKernelGGL(k_energy_backward<double>, dim3(ew_blocks(n)), dim3(kEW), 0, s, (const double*)Ia,
+    hipLaunchKernelGGL(k_energy_backward<double>, adjoint_grid(B, h, w), dim3(kEW), 0, s, (const double*)Ia,
                        (const double*)u, (const double*)Ib, lam, gE, (double*)dIa, (double*)du, (double*)dIb,
                        (const double*)du_c, (const double*)dIb_c, B, h, w);
   else
-    hipLaunchKernelGGL(k_energy_backward<float>, dim3(ew_blocks(n)), dim3(kEW), 0, s, (const float*)Ia,
+    hipLaunchKernelGGL(k_energy_backward<float>, adjoint_grid(B, h, w), dim3(kEW), 0, s, (const float*)Ia,
                        (const float*)u, (const float*)Ib, lam, gE, (float*)dIa, (float*)du,
                        (float*)dIb, (const float*)du_c, (const float*)dIb_c, B, h, w);
   return hipGetLastError();

@@ -150,14 +150,61 @@ def test_warp_adjoint_parity(rs, H, W):
     assert lhs == pytest.approx(rhs, rel=1e-12)
 
 
-@pytest.mark.parametrize("levels", [1, 2, 3])
-def test_pyramid_energy_and_backward_parity(rs, levels):
-    announce(f"pyramid energy levels={levels}")
-    rng = np.random.default_rng(levels)
-    B, H, W = 2, 64, 48
+@pytest.mark.parametrize("H,W,amp", [(150, 200, 3.0), (97, 130, 20.0), (64, 64, 9.0)])
+def test_warp_adjoint_joined_and_separate_taps(rs, H, W, amp):
+    """The adjoint joins shares that land on one cell (the lower taps of a
+    row with the upper taps of the next, a lane's right tap with its right
+    neighbour's left tap) before the atomic addition: groups of 8 rows with
+    a ragged last group and partial last wavefronts; amp 3 makes the taps
+    of neighbouring pixels mostly coincide, amp 9 and 20 (with the
+    per-pixel noise of the field) make many of them differ, and one item
+    mixes both."""
+    announce(f"warp_adjoint joins {H}x{W} amp {amp}")
+    rng = np.random.default_rng(H + W + int(amp))
+    B = 3
+    v = rng.standard_normal((B, H, W)).astype(np.float32)
+    u = smooth_field(rng, B, H, W, amp)
+    u[2, :, :, : W // 2] *= 0.1
+    base = rng.standard_normal((B, H, W)).astype(np.float32)
+    got = host(rs.warp_adjoint(gpu(v), gpu(u), gpu(base.copy())))
+    for b in range(B):
+        want = base[b].astype(np.float64) + oad.warp_adjoint(v[b].astype(np.float64), u[b].astype(np.float64),
+                                                             (H, W))
+        np.testing.assert_allclose(got[b], want, atol=2e-4, rtol=1e-5)
+
+
+def test_warp_adjoint_dot_product_full_size(rs):
+    """<warp(I), v> = <I, adjoint(v)> in float64 on the differentiation
+    workload's shape (64 x 512x512, a +-3 px field as in the benchmark, one
+    item with +-40 px): a property that holds at any size, checked per item."""
+    announce("warp_adjoint dot product 64x512x512")
+    B, H, W = 64, 512, 512
+    g = torch.Generator(device="cuda")
+    g.manual_seed(11)
+    I = torch.randn((B, H, W), device="cuda", dtype=torch.float64, generator=g)
+    v = torch.randn((B, H, W), device="cuda", dtype=torch.float64, generator=g)
+    yy = torch.arange(H, device="cuda", dtype=torch.float64).view(1, H, 1)
+    xx = torch.arange(W, device="cuda", dtype=torch.float64).view(1, 1, W)
+    ph = torch.rand((B, 1, 1), device="cuda", dtype=torch.float64, generator=g) * 6.28
+    u = torch.stack([3.0 * torch.sin(2 * np.pi * yy / H + ph) + 0.01 * xx,
+                     3.0 * torch.sin(2 * np.pi * xx / W + ph) + 0.01 * yy], dim=1).contiguous()
+    u[5] *= 13.0
+    lhs = (rs.warp(I, u) * v).sum(dim=(1, 2))
+    rhs = (I * rs.warp_adjoint(v, u)).sum(dim=(1, 2))
+    torch.testing.assert_close(lhs, rhs, rtol=1e-11, atol=1e-9)
+
+
+@pytest.mark.parametrize("levels,H,W,amp", [(1, 64, 48, 2.0), (2, 64, 48, 2.0), (3, 64, 48, 2.0),
+                                            (2, 132, 200, 2.0), (2, 90, 150, 16.0)])
+def test_pyramid_energy_and_backward_parity(rs, levels, H, W, amp):
+    """The backward pass's dIa scatter joins shares on one cell as the warp's
+    adjoint does: small and ragged shapes, smooth and rough fields."""
+    announce(f"pyramid energy levels={levels} {H}x{W} amp {amp}")
+    rng = np.random.default_rng(levels + H)
+    B = 2
     Ia = rng.standard_normal((B, H, W)).astype(np.float32)
     Ib = rng.standard_normal((B, H, W)).astype(np.float32)
-    u = smooth_field(rng, B, H, W, 2.0)
+    u = smooth_field(rng, B, H, W, amp)
     gE = torch.tensor([1.0, -0.5], dtype=torch.float64, device="cuda")
     E = host(rs.pyramid_energy(gpu(Ia), gpu(u), gpu(Ib), 0.1, levels))
     dIa, du, dIb = (host(t) for t in rs.pyramid_energy_backward(gpu(Ia), gpu(u), gpu(Ib), 0.1, levels, gE))
