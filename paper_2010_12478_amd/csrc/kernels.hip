@@ -142,8 +142,9 @@ __global__ void __launch_bounds__(kEW) k_warp(const S* __restrict__ T, const S* 
 __device__ __forceinline__ void atomic_add(float* p, float v) { unsafeAtomicAdd(p, v); }
 __device__ __forceinline__ void atomic_add(double* p, double v) { unsafeAtomicAdd(p, v); }
 
-// Scatters of the adjoint kernels.  A thread takes kAdjRows consecutive rows
-// of one column; the bilinear shares of a pixel go to two upper taps (row
+// Scatters of the adjoint kernels.  A thread takes a group of consecutive
+// rows of one column (kWarpAdjRows for the warp's adjoint, kBackRows for the
+// energy's backward pass, which holds more per row); the bilinear shares of a pixel go to two upper taps (row
 // ya) and two lower taps (row yb).  Shares that land on one cell are added
 // in registers before the single atomic addition that carries them:
 //  - rows: the lower taps of row y are held back and joined to the upper
@@ -154,7 +155,7 @@ __device__ __forceinline__ void atomic_add(double* p, double v) { unsafeAtomicAd
 // On smooth fields that leaves about one full-wavefront atomic per row of
 // pixels instead of four.  The order of the additions is not fixed (as with
 // any atomic sum).
-constexpr int kAdjRows = 8;
+constexpr int kWarpAdjRows = 16, kBackRows = 4;   // measured best of 4, 8, 16
 
 template <typename S>
 struct TapPair {   // two horizontally adjacent taps of one row; y < 0: none
@@ -226,10 +227,10 @@ struct RowScatter {
   }
 };
 
-// Grid of the adjoint kernels: column blocks x (item, group of kAdjRows rows),
+// Grid of the adjoint kernels: column blocks x (item, group of `rows` rows),
 // at most 65535 groups (grid-strided beyond).
-inline dim3 adjoint_grid(int B, int H, int W) {
-  const long long groups = (long long)B * ((H + kAdjRows - 1) / kAdjRows);
+inline dim3 adjoint_grid(int B, int H, int W, int rows) {
+  const long long groups = (long long)B * ((H + rows - 1) / rows);
   return dim3((unsigned)((W + kEW - 1) / kEW), (unsigned)(groups < 65535 ? groups : 65535));
 }
 
@@ -241,14 +242,14 @@ __global__ void __launch_bounds__(kEW) k_warp_adjoint(const S* __restrict__ g, c
   const int x = blockIdx.x * kEW + threadIdx.x;
   const bool col = x < W;
   const int xl = col ? x : W - 1;   // loads of lanes past the last column: any pixel
-  const int gpi = (H + kAdjRows - 1) / kAdjRows;
+  const int gpi = (H + kWarpAdjRows - 1) / kWarpAdjRows;
   for (long long t = blockIdx.y; t < (long long)B * gpi; t += gridDim.y) {   // wave-uniform
-    const int b = (int)(t / gpi), y0 = (int)(t - (long long)b * gpi) * kAdjRows;
+    const int b = (int)(t / gpi), y0 = (int)(t - (long long)b * gpi) * kWarpAdjRows;
     const S* ub = u + (size_t)b * 2 * HW;
     const S* gb = g + (size_t)b * HW;
-    S vx[kAdjRows], vy[kAdjRows], vg[kAdjRows];
+    S vx[kWarpAdjRows], vy[kWarpAdjRows], vg[kWarpAdjRows];
 #pragma unroll
-    for (int k = 0; k < kAdjRows; ++k) {
+    for (int k = 0; k < kWarpAdjRows; ++k) {
       const int r = min(y0 + k, H - 1) * W + xl;
       vx[k] = ub[r];
       vy[k] = ub[HW + r];
@@ -257,7 +258,7 @@ __global__ void __launch_bounds__(kEW) k_warp_adjoint(const S* __restrict__ g, c
     RowScatter<S> sc;
     S* tb = gT + (size_t)b * HW;
 #pragma unroll
-    for (int k = 0; k < kAdjRows; ++k)
+    for (int k = 0; k < kWarpAdjRows; ++k)
       sc.pixel(tb, H, W, col && y0 + k < H, x, y0 + k, vx[k], vy[k], (double)vg[k]);
     sc.finish(tb, W);
   }
@@ -316,18 +317,18 @@ __global__ void __launch_bounds__(kEW) k_energy_backward(const S* __restrict__ I
   const size_t HWc = (size_t)hc * wc;
   const int x = blockIdx.x * kEW + threadIdx.x;
   const bool col = x < W;
-  const int gpi = (H + kAdjRows - 1) / kAdjRows;
+  const int gpi = (H + kBackRows - 1) / kBackRows;
   for (long long t = blockIdx.y; t < (long long)B * gpi; t += gridDim.y) {   // wave-uniform
-    const int b = (int)(t / gpi), y0 = (int)(t - (long long)b * gpi) * kAdjRows;
+    const int b = (int)(t / gpi), y0 = (int)(t - (long long)b * gpi) * kBackRows;
     const S* ux = u + (size_t)b * 2 * HW;
     const S* uy = ux + HW;
     const double w = gE[b];
     // the rows' outputs du and dIb first (their loads free to overlap: the
     // inputs are restrict), the scatters of dIa after them
-    S sx[kAdjRows], sy[kAdjRows];
-    double sv[kAdjRows];
+    S sx[kBackRows], sy[kBackRows];
+    double sv[kBackRows];
 #pragma unroll
-    for (int k = 0; k < kAdjRows; ++k) {
+    for (int k = 0; k < kBackRows; ++k) {
       sx[k] = sy[k] = S(0);
       sv[k] = 0.0;
       const int y = y0 + k;
@@ -367,7 +368,7 @@ __global__ void __launch_bounds__(kEW) k_energy_backward(const S* __restrict__ I
     RowScatter<S> sc;
     S* db = dIa + (size_t)b * HW;
 #pragma unroll
-    for (int k = 0; k < kAdjRows; ++k) sc.pixel(db, H, W, col && y0 + k < H, x, y0 + k, sx[k], sy[k], sv[k]);
+    for (int k = 0; k < kBackRows; ++k) sc.pixel(db, H, W, col && y0 + k < H, x, y0 + k, sx[k], sy[k], sv[k]);
     sc.finish(db, W);
   }
 }
@@ -471,10 +472,10 @@ hipError_t launch_warp_adjoint(const void* g, const void* u, void* gT, int B, in
                                hipStream_t s) {
   if ((size_t)B * H * W == 0) return hipSuccess;
   if (f64)
-    hipLaunchKernelGGL(k_warp_adjoint<double>, adjoint_grid(B, H, W), dim3(kEW), 0, s, (const double*)g,
+    hipLaunchKernelGGL(k_warp_adjoint<double>, adjoint_grid(B, H, W, kWarpAdjRows), dim3(kEW), 0, s, (const double*)g,
                        (const double*)u, (double*)gT, B, H, W);
   else
-    hipLaunchKernelGGL(k_warp_adjoint<float>, adjoint_grid(B, H, W), dim3(kEW), 0, s, (const float*)g,
+    hipLaunchKernelGGL(k_warp_adjoint<float>, adjoint_grid(B, H, W, kWarpAdjRows), dim3(kEW), 0, s, (const float*)g,
                        (const float*)u, (float*)gT, B, H, W);
   return hipGetLastError();
 }
@@ -521,11 +522,11 @@ hipError_t launch_energy_backward_level(const void* Ia, const void* u, const voi
   const size_t n = (size_t)B * h * w;
   if (n == 0) return hipSuccess;
   if (f64)
-    hipLaunchKernelGGL(k_energy_backward<double>, adjoint_grid(B, h, w), dim3(kEW), 0, s, (const double*)Ia,
+    hipLaunchKernelGGL(k_energy_backward<double>, adjoint_grid(B, h, w, kBackRows), dim3(kEW), 0, s, (const double*)Ia,
                        (const double*)u, (const double*)Ib, lam, gE, (double*)dIa, (double*)du, (double*)dIb,
                        (const double*)du_c, (const double*)dIb_c, B, h, w);
   else
-    hipLaunchKernelGGL(k_energy_backward<float>, adjoint_grid(B, h, w), dim3(kEW), 0, s, (const float*)Ia,
+    hipLaunchKernelGGL(k_energy_backward<float>, adjoint_grid(B, h, w, kBackRows), dim3(kEW), 0, s, (const float*)Ia,
                        (const float*)u, (const float*)Ib, lam, gE, (float*)dIa, (float*)du,
                        (float*)dIb, (const float*)du_c, (const float*)dIb_c, B, h, w);
   return hipGetLastError();

@@ -154,7 +154,7 @@ def test_warp_adjoint_parity(rs, H, W):
 def test_warp_adjoint_joined_and_separate_taps(rs, H, W, amp):
     """The adjoint joins shares that land on one cell (the lower taps of a
     row with the upper taps of the next, a lane's right tap with its right
-    neighbour's left tap) before the atomic addition: groups of 8 rows with
+    neighbour's left tap) before the atomic addition: groups of 16 rows with
     a ragged last group and partial last wavefronts; amp 3 makes the taps
     of neighbouring pixels mostly coincide, amp 9 and 20 (with the
     per-pixel noise of the field) make many of them differ, and one item
