@@ -144,7 +144,7 @@ __device__ __forceinline__ void atomic_add(double* p, double v) { unsafeAtomicAd
 
 // Scatters of the adjoint kernels.  A thread takes a group of consecutive
 // rows of one column (kWarpAdjRows for the warp's adjoint, kBackRows for the
-// energy's backward pass, which holds more per row); the bilinear shares of a pixel go to two upper taps (row
+// energy's backward pass); the bilinear shares of a pixel go to two upper taps (row
 // ya) and two lower taps (row yb).  Shares that land on one cell are added
 // in registers before the single atomic addition that carries them:
 //  - rows: the lower taps of row y are held back and joined to the upper
@@ -155,7 +155,7 @@ __device__ __forceinline__ void atomic_add(double* p, double v) { unsafeAtomicAd
 // On smooth fields that leaves about one full-wavefront atomic per row of
 // pixels instead of four.  The order of the additions is not fixed (as with
 // any atomic sum).
-constexpr int kWarpAdjRows = 16, kBackRows = 4;   // measured best of 4, 8, 16
+constexpr int kWarpAdjRows = 16, kBackRows = 8;   // measured best of 4, 8, 16 (adjoint) and 2, 4, 8 (backward)
 
 template <typename S>
 struct TapPair {   // two horizontally adjacent taps of one row; y < 0: none
@@ -323,6 +323,28 @@ __global__ void __launch_bounds__(kEW) k_energy_backward(const S* __restrict__ I
     const S* ux = u + (size_t)b * 2 * HW;
     const S* uy = ux + HW;
     const double w = gE[b];
+    // u on the rows y0 - 1 .. y0 + kBackRows (clamped to the image; lanes
+    // past the last column read column W - 1): the rows above and below a
+    // pixel come from these registers, the columns left and right from the
+    // neighbouring lanes, and lanes 0 and 63 load the columns beyond the
+    // wavefront's 64
+    const int lane = threadIdx.x & (kWave - 1);
+    const int xl = col ? x : W - 1;
+    S cu[kBackRows + 2], cv[kBackRows + 2], eu[kBackRows], ev[kBackRows];
+#pragma unroll
+    for (int k = 0; k < kBackRows + 2; ++k) {
+      const int r = clampi(y0 - 1 + k, 0, H - 1) * W + xl;
+      cu[k] = ux[r];
+      cv[k] = uy[r];
+    }
+    const int xe = lane == 0 ? x - 1 : x + 1;   // lane 0: the column left of it, lane 63: right
+    const bool edge = col && (lane == 0 || lane == kWave - 1) && xe >= 0 && xe < W;
+#pragma unroll
+    for (int k = 0; k < kBackRows; ++k) {
+      const int r = min(y0 + k, H - 1) * W + xe;
+      eu[k] = edge ? ux[r] : S(0);
+      ev[k] = edge ? uy[r] : S(0);
+    }
     // the rows' outputs du and dIb first (their loads free to overlap: the
     // inputs are restrict), the scatters of dIa after them
     S sx[kBackRows], sy[kBackRows];
@@ -331,11 +353,14 @@ __global__ void __launch_bounds__(kEW) k_energy_backward(const S* __restrict__ I
     for (int k = 0; k < kBackRows; ++k) {
       sx[k] = sy[k] = S(0);
       sv[k] = 0.0;
+      const S cxs = cu[k + 1], cys = cv[k + 1];
+      // all lanes take part in the lane shifts
+      const S lxs = wave_from_left(cxs, eu[k]), lys = wave_from_left(cys, ev[k]);
+      const S rxs = wave_from_right(cxs, eu[k]), rys = wave_from_right(cys, ev[k]);
       const int y = y0 + k;
       if (!col || y >= H) continue;
       const int r = y * W + x;
       const size_t q = (size_t)b * HW + r;
-      const S cxs = ux[r], cys = uy[r];
       int ix, iy;
       double fx, fy;
       cell_of(cxs, ix, fx);
@@ -345,10 +370,10 @@ __global__ void __launch_bounds__(kEW) k_energy_backward(const S* __restrict__ I
       const double res = s - (double)Ib[q];
       const double cx = cxs, cy = cys;
       double nbx = 0.0, nby = 0.0;
-      if (x > 0) { nbx += cx - (double)ux[r - 1]; nby += cy - (double)uy[r - 1]; }
-      if (x + 1 < W) { nbx += cx - (double)ux[r + 1]; nby += cy - (double)uy[r + 1]; }
-      if (y > 0) { nbx += cx - (double)ux[r - W]; nby += cy - (double)uy[r - W]; }
-      if (y + 1 < H) { nbx += cx - (double)ux[r + W]; nby += cy - (double)uy[r + W]; }
+      if (x > 0) { nbx += cx - (double)lxs; nby += cy - (double)lys; }
+      if (x + 1 < W) { nbx += cx - (double)rxs; nby += cy - (double)rys; }
+      if (y > 0) { nbx += cx - (double)cu[k]; nby += cy - (double)cv[k]; }
+      if (y + 1 < H) { nbx += cx - (double)cu[k + 2]; nby += cy - (double)cv[k + 2]; }
       double gx = w * (2.0 * res * dsx + 2.0 * lam * nbx);
       double gy = w * (2.0 * res * dsy + 2.0 * lam * nby);
       double gb = w * (-2.0 * res);
