@@ -143,10 +143,11 @@ __device__ __forceinline__ void atomic_add(float* p, float v) { unsafeAtomicAdd(
 __device__ __forceinline__ void atomic_add(double* p, double v) { unsafeAtomicAdd(p, v); }
 
 // Scatters of the adjoint kernels.  A thread takes a group of consecutive
-// rows of one column (kWarpAdjRows for the warp's adjoint, kBackRows for the
-// energy's backward pass); the bilinear shares of a pixel go to two upper taps (row
-// ya) and two lower taps (row yb).  Shares that land on one cell are added
-// in registers before the single atomic addition that carries them:
+// rows of one column (kWarpAdjRows for the warp's adjoint, kBackRows for
+// the energy's backward pass); the bilinear shares of a pixel go to two
+// upper taps (row ya) and two lower taps (row yb).  Shares that land on one
+// cell are added in registers before the single atomic addition that
+// carries them:
 //  - rows: the lower taps of row y are held back and joined to the upper
 //    taps of row y + 1 when those are the same two cells (the common case of
 //    a smooth field); otherwise they are added to the destination;
@@ -155,7 +156,8 @@ __device__ __forceinline__ void atomic_add(double* p, double v) { unsafeAtomicAd
 // On smooth fields that leaves about one full-wavefront atomic per row of
 // pixels instead of four.  The order of the additions is not fixed (as with
 // any atomic sum).
-constexpr int kWarpAdjRows = 16, kBackRows = 8;   // measured best of 4, 8, 16 (adjoint) and 2, 4, 8 (backward)
+// measured best of 4, 8, 16 rows (adjoint) and of 2, 4, 8 (backward)
+constexpr int kWarpAdjRows = 16, kBackRows = 8;
 
 template <typename S>
 struct TapPair {   // two horizontally adjacent taps of one row; y < 0: none
