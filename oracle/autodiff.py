@@ -1,7 +1,8 @@
 """Differentiation of the warp + energy step, CPU oracle.  TEST INFRASTRUCTURE ONLY.
 
-Energy of a batch item, over a pyramid of ``levels`` levels built by 2x2 box
-restriction of both images and half-box restriction of the displacement:
+Energy of a batch item, over a pyramid of ``levels`` levels built by the
+binomial frame restriction of both images and half the 2x2 block mean of the
+displacement (the restrictions of the registration's multilevel scheme):
 
     E(I_a, u, I_b) = sum_l [ sum_x (I_a^l(x + u^l(x)) - I_b^l(x))^2
                              + lam |grad u^l|^2 ]
@@ -15,8 +16,8 @@ from __future__ import annotations
 
 import numpy as np
 
-from .registration import (energy, energy_and_gradient, restrict_field,
-                           restrict_image, sample_displaced, split_offset)
+from .registration import (BINOMIAL6, energy, energy_and_gradient, restrict_field,
+                           restrict_frame, restrict_image, sample_displaced, split_offset)
 
 
 def warp_adjoint(v, u, shape):
@@ -46,12 +47,29 @@ def restrict_field_adjoint(gc):
     return np.stack([0.5 * restrict_image_adjoint(gc[0]), 0.5 * restrict_image_adjoint(gc[1])])
 
 
+def restrict_frame_adjoint(gc, shape):
+    """Transpose of the binomial frame restriction: every coarse value is
+    scattered with weight w_a w_b into the (clamped) fine taps it was formed
+    from."""
+    H, W = shape
+    h, w = gc.shape
+    ys, xs = np.arange(h), np.arange(w)
+    out = np.zeros(shape)
+    for a in range(6):
+        ya = np.clip(2 * ys + a - 2, 0, H - 1)
+        for b in range(6):
+            xb = np.clip(2 * xs + b - 2, 0, W - 1)
+            Y, X = np.meshgrid(ya, xb, indexing="ij")
+            np.add.at(out, (Y, X), BINOMIAL6[a] * BINOMIAL6[b] * gc)
+    return out
+
+
 def _levels(Ia, u, Ib, levels):
     A, U, B = [np.asarray(Ia, np.float64)], [np.asarray(u, np.float64)], [np.asarray(Ib, np.float64)]
     for _ in range(levels - 1):
-        A.append(restrict_image(A[-1]))
+        A.append(restrict_frame(A[-1]))
         U.append(restrict_field(U[-1]))
-        B.append(restrict_image(B[-1]))
+        B.append(restrict_frame(B[-1]))
     return A, U, B
 
 
@@ -74,7 +92,7 @@ def pyramid_energy_grads(Ia, u, Ib, lam, levels=1):
         if gA is None:
             gA, gU, gB = ga, gu, gb
         else:
-            gA = ga + restrict_image_adjoint(gA)
+            gA = ga + restrict_frame_adjoint(gA, A[l].shape)
             gU = gu + restrict_field_adjoint(gU)
-            gB = gb + restrict_image_adjoint(gB)
+            gB = gb + restrict_frame_adjoint(gB, B[l].shape)
     return E, gA, gU, gB

@@ -20,14 +20,23 @@ pyramid.  T is sampled bilinearly with edge-clamped taps.
 Array conventions: images [H][W] (row y, column x), displacements [2][H][W]
 with plane 0 = x and plane 1 = y, pixel centres on integer coordinates.
 
-Storage precision.  Stored data are 32-bit floats: the frames, their pyramid
-levels, and every displacement field the solver keeps (the initial guess on
-the coarsest level, each gradient-descent iterate, each prolongation) - the
-paper moves a deformation as single-precision floats (Section 5: 20 bytes of
-deformation data and indices per message).  All arithmetic is float64; a
-stored value is the float64 result rounded to float32 (``f32``).  The integer
-part of a displacement (which bilinear cell a sample falls in) is therefore
-decided on a float32 value.
+Frame pyramid.  Each coarser level of a frame is a separable binomial
+low-pass of the level below, sampled at the centres of its 2x2 blocks (the
+restriction of images is not specified by the paper beyond "multilevel";
+a 2x2 block mean would alias periodic content that the coarse grid cannot
+resolve, see ``restrict_frame``).  Displacements are restricted by half the
+2x2 block mean.
+
+Storage precision (two modes).  ``storage="f32"``: every value the solver
+keeps - frame pyramid levels, the initial guess on the coarsest level, each
+gradient-descent iterate, each prolongation - is the float64 result rounded
+once to float32, and the integer cell of a bilinear sample is decided on the
+float32 value of the displacement.  The paper fixes no precision for these
+values; this mode exists so that a GPU implementation that stores its fields
+in float32 (and computes in float64) can be compared with the oracle bit for
+bit.  ``storage="f64"``: plain float64 throughout - the frames (given as
+float32 data) are the only rounded values.  The two modes differ by the
+float32 roundings of the stored fields and their consequences.
 """
 from __future__ import annotations
 
@@ -49,10 +58,25 @@ def f32(a):
     return np.asarray(a, dtype=np.float64).astype(np.float32).astype(np.float64)
 
 
-def split_offset(off):
-    """Integer cell offset (decided in float32) and the float64 remainder."""
-    cell = np.floor(np.asarray(off, dtype=np.float64).astype(np.float32)).astype(np.float64)
-    return cell.astype(np.int64), np.asarray(off, dtype=np.float64) - cell
+def store(a, storage="f32"):
+    """A value as the solver keeps it: rounded to float32 (``"f32"``) or the
+    float64 result itself (``"f64"``)."""
+    if storage == "f32":
+        return f32(a)
+    if storage == "f64":
+        return np.array(a, dtype=np.float64)
+    raise ValueError(f"unknown storage mode {storage!r}")
+
+
+def split_offset(off, storage="f32"):
+    """Integer cell offset and the float64 remainder.  In float32 storage the
+    cell is decided on the float32 value of the offset, else on the value."""
+    off = np.asarray(off, dtype=np.float64)
+    if storage == "f32":
+        cell = np.floor(off.astype(np.float32)).astype(np.float64)
+    else:
+        cell = np.floor(off)
+    return cell.astype(np.int64), off - cell
 
 
 def bilinear(img, xi, yi, wx, wy):
@@ -78,27 +102,27 @@ def bilinear(img, xi, yi, wx, wy):
     return s, dsx, dsy
 
 
-def sample_displaced(img, u):
+def sample_displaced(img, u, storage="f32"):
     """img(x + u(x)) for every pixel x of u's grid, with derivatives."""
     h, w = u.shape[1:]
     yy, xx = np.mgrid[0:h, 0:w]
-    cx, fx = split_offset(u[0])
-    cy, fy = split_offset(u[1])
+    cx, fx = split_offset(u[0], storage)
+    cy, fy = split_offset(u[1], storage)
     return bilinear(img, xx + cx, yy + cy, fx, fy)
 
 
-def warp(T, u):
+def warp(T, u, storage="f32"):
     """(T o phi)(x) = T(x + u(x)) (the deformed template)."""
-    return sample_displaced(T, u)[0]
+    return sample_displaced(T, u, storage)[0]
 
 
 # ----------------------------------------------------------------------------
 # Energy and gradient
 # ----------------------------------------------------------------------------
 
-def energy(R, T, u, lam):
+def energy(R, T, u, lam, storage="f32"):
     """E(u): SSD of the warped template against R plus lam * |grad u|^2."""
-    r = warp(T, u) - R
+    r = warp(T, u, storage) - R
     reg = 0.0
     for c in range(2):
         dx = u[c][:, 1:] - u[c][:, :-1]   # pairs (x, x+e1) inside the grid
@@ -117,11 +141,11 @@ def neighbour_differences(v):
     return out
 
 
-def energy_and_gradient(R, T, u, lam):
+def energy_and_gradient(R, T, u, lam, storage="f32"):
     """E(u) and dE/du (exact away from integer sample positions)."""
-    s, dsx, dsy = sample_displaced(T, u)
+    s, dsx, dsy = sample_displaced(T, u, storage)
     r = s - R
-    E = energy(R, T, u, lam)
+    E = energy(R, T, u, lam, storage)
     g = np.empty_like(u)
     g[0] = 2 * r * dsx + 2 * lam * neighbour_differences(u[0])
     g[1] = 2 * r * dsy + 2 * lam * neighbour_differences(u[1])
@@ -133,7 +157,7 @@ def energy_and_gradient(R, T, u, lam):
 # ----------------------------------------------------------------------------
 
 def restrict_image(F):
-    """Next coarser pyramid level: mean over 2x2 blocks."""
+    """Mean over 2x2 blocks (the restriction of displacement fields)."""
     return 0.25 * (F[0::2, 0::2] + F[0::2, 1::2] + F[1::2, 0::2] + F[1::2, 1::2])
 
 
@@ -142,12 +166,58 @@ def restrict_field(u):
     return np.stack([0.5 * restrict_image(u[0]), 0.5 * restrict_image(u[1])])
 
 
-def pyramid(F, levels):
-    """Stored frame pyramid: each level is the 2x2 block mean of the stored
-    level below, rounded to float32."""
-    out = [f32(F)]
+# Per-axis weights of the frame restriction: the binomial coefficients of
+# (1 + z)^5 over 32.  Their frequency response is cos(pi f)^5 (f in cycles per
+# fine pixel): 1 at f = 0, 0.18 at f = 1/4 (the coarse grid's Nyquist
+# frequency), 0 at f = 1/2; the 2x2 block mean, the binomial of order 1, has
+# cos(pi f) = 0.71 at f = 1/4.
+BINOMIAL6 = (1 / 32, 5 / 32, 10 / 32, 10 / 32, 5 / 32, 1 / 32)
+
+
+def restrict_frame(F):
+    """Next coarser level of a frame: at coarse pixel (Y, X)
+
+        sum_{a=0..5} w_a sum_{b=0..5} w_b F[2Y + a - 2][2X + b - 2]
+
+    with w = BINOMIAL6 and edge-clamped taps, i.e. the separable binomial
+    low-pass centred on (2Y + 1/2, 2X + 1/2), the centre of the 2x2 block the
+    coarse pixel covers (the geometry of the block mean and of the
+    prolongation).  The paper's multilevel scheme (Section 2.3.1) does not say
+    how images are coarsened.  A lattice whose period is at most two pixels
+    of the coarse grid (at least 1/4 cycle per fine pixel) cannot be
+    represented there: at exactly two pixels the sampled lattice no longer
+    tells a shift from its mirror image, below two it aliases to a lattice
+    that moves the other way, and a solve on that level pulls the
+    displacement away from the true shift.  The 2x2 block mean passes such
+    content at up to 71% of its amplitude, the order-5 binomial at most 18%,
+    while it keeps 67% of a lattice of four coarse pixels per period.
+
+    Evaluation order: per row a, the weighted taps summed over b in
+    increasing order; then the weighted row sums over a in increasing order
+    (every product is exact: the weights have three significant bits).
+    """
+    H, W = F.shape
+    ys = np.arange(H // 2)
+    xs = np.arange(W // 2)
+    out = None
+    for a in range(6):
+        ya = np.clip(2 * ys + a - 2, 0, H - 1)
+        row = None
+        for b in range(6):
+            xb = np.clip(2 * xs + b - 2, 0, W - 1)
+            t = BINOMIAL6[b] * F[np.ix_(ya, xb)]
+            row = t if row is None else row + t
+        t = BINOMIAL6[a] * row
+        out = t if out is None else out + t
+    return out
+
+
+def pyramid(F, levels, storage="f32"):
+    """Stored frame pyramid: level 0 is the frame, each coarser level the
+    binomial restriction of the stored level below, stored."""
+    out = [store(F, storage)]
     for _ in range(levels - 1):
-        out.append(f32(restrict_image(out[-1])))
+        out.append(store(restrict_frame(out[-1]), storage))
     return out
 
 
@@ -174,7 +244,7 @@ class LevelResult:
     energies: list
 
 
-def solve_level(R, T, u0, tau, lam, max_iter, fixed_iter, rel_tol):
+def solve_level(R, T, u0, tau, lam, max_iter, fixed_iter, rel_tol, storage="f32"):
     """Gradient descent on one pyramid level.
 
     Iteration t evaluates E_t and g_t at u_t.  Unless the iteration count is
@@ -182,20 +252,20 @@ def solve_level(R, T, u0, tau, lam, max_iter, fixed_iter, rel_tol):
     E_{t-1} - E_t is at most rel_tol * E_{t-1} (this includes any increase);
     otherwise it steps u_{t+1} = u_t - tau g_t (stored in float32).  After
     max_iter steps it returns u_{max_iter}.  A non-finite energy stops the
-    solve at once.
+    solve at once.  Iterates are stored per ``storage``.
     """
-    u = f32(u0)
+    u = store(u0, storage)
     e_prev = None
     energies = []
     for t in range(max_iter):
-        E, g = energy_and_gradient(R, T, u, lam)
+        E, g = energy_and_gradient(R, T, u, lam, storage)
         energies.append(E)
         if not np.isfinite(E):
             return LevelResult(u, t, STATUS_NONFINITE, energies)
         if not fixed_iter and e_prev is not None and (e_prev - E) <= rel_tol * e_prev:
             return LevelResult(u, t, STATUS_OK, energies)
         e_prev = E
-        u = f32(u - tau * g)
+        u = store(u - tau * g, storage)
     status = STATUS_OK if fixed_iter else STATUS_MAXITER
     return LevelResult(u, max_iter, status, energies)
 
@@ -207,7 +277,7 @@ class RegResult:
     status: int
 
 
-def register(R_pyr, T_pyr, u0, params):
+def register(R_pyr, T_pyr, u0, params, storage="f32"):
     """Multilevel registration Reg(R, T, u0).
 
     The initial guess (zero when u0 is None) is restricted to the coarsest
@@ -222,15 +292,15 @@ def register(R_pyr, T_pyr, u0, params):
         u = np.array(u0, dtype=np.float64)
         for _ in range(L - 1):
             u = restrict_field(u)
-        u = f32(u)
+        u = store(u, storage)
     iters = [0] * L
     status = STATUS_OK
     for lvl in range(L - 1, -1, -1):
         if lvl < L - 1:
             h, w = R_pyr[lvl].shape
-            u = f32(prolong_field(u, h, w))
+            u = store(prolong_field(u, h, w), storage)
         res = solve_level(R_pyr[lvl], T_pyr[lvl], u, params.tau, params.lam,
-                          params.max_iter, params.fixed_iter, params.rel_tol)
+                          params.max_iter, params.fixed_iter, params.rel_tol, storage)
         u, iters[lvl] = res.u, res.iters
         status |= res.status
         if res.status & STATUS_NONFINITE:
@@ -245,23 +315,23 @@ def register(R_pyr, T_pyr, u0, params):
 # Series operators A and B (Section 2.3.2) and the scan operator (Section 3)
 # ----------------------------------------------------------------------------
 
-def compose(u_ij, u_jk):
+def compose(u_ij, u_jk, storage="f32"):
     """Displacement of phi_jk o phi_ij: u_ij(x) + u_jk(x + u_ij(x))."""
     h, w = u_ij.shape[1:]
     yy, xx = np.mgrid[0:h, 0:w]
-    cx, fx = split_offset(u_ij[0])
-    cy, fy = split_offset(u_ij[1])
+    cx, fx = split_offset(u_ij[0], storage)
+    cy, fy = split_offset(u_ij[1], storage)
     out = np.empty_like(u_ij, dtype=np.float64)
     for c in range(2):
         out[c] = u_ij[c] + bilinear(u_jk[c], xx + cx, yy + cy, fx, fy)[0]
     return out
 
 
-def op_A(pyrs, i, params):
+def op_A(pyrs, i, params, storage="f32"):
     """A(f_i, f_{i+1}): register consecutive frames from the identity."""
-    return register(pyrs[i], pyrs[i + 1], None, params)
+    return register(pyrs[i], pyrs[i + 1], None, params, storage)
 
 
-def op_B(pyrs, i, k, u_ij, u_jk, params):
+def op_B(pyrs, i, k, u_ij, u_jk, params, storage="f32"):
     """B(phi_ij, phi_jk) = phi_ik: register f_i and f_k from the composition."""
-    return register(pyrs[i], pyrs[k], compose(u_ij, u_jk), params)
+    return register(pyrs[i], pyrs[k], compose(u_ij, u_jk, storage), params, storage)

@@ -18,19 +18,20 @@ from .registration import op_A, op_B, pyramid
 _POOL_STATE = {}
 
 
-def _init_worker(pyrs, params):
+def _init_worker(pyrs, params, storage="f32"):
     _POOL_STATE["pyrs"] = pyrs
     _POOL_STATE["params"] = params
+    _POOL_STATE["storage"] = storage
 
 
 def _run_A(i):
-    r = op_A(_POOL_STATE["pyrs"], i, _POOL_STATE["params"])
+    r = op_A(_POOL_STATE["pyrs"], i, _POOL_STATE["params"], _POOL_STATE["storage"])
     return r.u, r.iters, r.status
 
 
 def _run_B(args):
     i, k, u_ij, u_jk = args
-    r = op_B(_POOL_STATE["pyrs"], i, k, u_ij, u_jk, _POOL_STATE["params"])
+    r = op_B(_POOL_STATE["pyrs"], i, k, u_ij, u_jk, _POOL_STATE["params"], _POOL_STATE["storage"])
     return r.u, r.iters, r.status
 
 
@@ -43,29 +44,30 @@ class ScanResult:
     ops: np.ndarray       # the plan
 
 
-def frame_pyramids(frames, levels):
-    return [pyramid(np.asarray(f, dtype=np.float64), levels) for f in frames]
+def frame_pyramids(frames, levels, storage="f32"):
+    return [pyramid(np.asarray(f, dtype=np.float64), levels, storage) for f in frames]
 
 
-def _map(fn, items, workers, pyrs, params):
+def _map(fn, items, workers, pyrs, params, storage="f32"):
     if workers <= 1 or len(items) <= 1:
-        _init_worker(pyrs, params)
+        _init_worker(pyrs, params, storage)
         return [fn(x) for x in items]
     import multiprocessing as mp
     ctx = mp.get_context("fork")
     with ctx.Pool(min(workers, len(items)), initializer=_init_worker,
-                  initargs=(pyrs, params)) as pool:
+                  initargs=(pyrs, params, storage)) as pool:
         return pool.map(fn, items)
 
 
 def run_scan(frames, params, algo="seq", chunk=0, global_algo="lf", workers=1,
-             pyrs=None):
-    """Register every frame of ``frames`` ([N][H][W]) to frame 0."""
+             pyrs=None, storage="f32"):
+    """Register every frame of ``frames`` ([N][H][W]) to frame 0 (``storage``:
+    see ``oracle.registration``)."""
     N = len(frames)
     M = N - 1
     if pyrs is None:
-        pyrs = frame_pyramids(frames, params.levels)
-    A = _map(_run_A, list(range(M)), workers, pyrs, params)
+        pyrs = frame_pyramids(frames, params.levels, storage)
+    A = _map(_run_A, list(range(M)), workers, pyrs, params, storage)
     ops, n_levels = plans.make_plan(M, algo, chunk, global_algo)
     node = {m: A[m][0] for m in range(M)}
     iters = [A[m][1] for m in range(M)] + [None] * len(ops)
@@ -74,7 +76,7 @@ def run_scan(frames, params, algo="seq", chunk=0, global_algo="lf", workers=1,
         rows = [n for n in range(len(ops)) if ops[n, 0] == lvl]
         args = [(int(ops[n, 4]), int(ops[n, 6]), node[int(ops[n, 2])], node[int(ops[n, 3])])
                 for n in rows]
-        res = _map(_run_B, args, workers, pyrs, params)
+        res = _map(_run_B, args, workers, pyrs, params, storage)
         for n, (u, it, st) in zip(rows, res):
             node[int(ops[n, 1])] = u
             iters[M + n] = it

@@ -93,13 +93,23 @@ def lattice_image(spec: SeriesSpec, origin, qx: torch.Tensor, qy: torch.Tensor) 
     return out
 
 
-def make_series(spec: SeriesSpec, device="cpu", frames_dtype=torch.float32) -> Series:
-    """Generate the frame series of ``spec`` on ``device``."""
+def _window_grid(spec: SeriesSpec, window, dev):
+    """Pixel coordinates of the frame, or of the window (y0, x0, h, w) of it:
+    a crop that keeps the full frame's distortion (its period is the full
+    height and width) and drift."""
+    y0, x0, h, w = (0, 0, spec.height, spec.width) if window is None else window
+    return torch.meshgrid(torch.arange(y0, y0 + h, dtype=torch.float64, device=dev),
+                          torch.arange(x0, x0 + w, dtype=torch.float64, device=dev), indexing="ij")
+
+
+def make_series(spec: SeriesSpec, device="cpu", frames_dtype=torch.float32, window=None) -> Series:
+    """Generate the frame series of ``spec`` on ``device`` (only the pixels of
+    ``window`` = (y0, x0, h, w) if given)."""
     origin, drift, theta, noisy = _frame_params(spec)
     dev = torch.device(device)
-    H, W, N = spec.height, spec.width, spec.n_frames
-    yy, xx = torch.meshgrid(torch.arange(H, dtype=torch.float64, device=dev),
-                            torch.arange(W, dtype=torch.float64, device=dev), indexing="ij")
+    N = spec.n_frames
+    yy, xx = _window_grid(spec, window, dev)
+    H, W = yy.shape
     gen = torch.Generator(device=dev)
     gen.manual_seed(spec.seed)
     frames = torch.empty((N, H, W), dtype=frames_dtype, device=dev)
@@ -115,12 +125,11 @@ def make_series(spec: SeriesSpec, device="cpu", frames_dtype=torch.float32) -> S
     return Series(spec, frames, drift, theta, origin, noisy)
 
 
-def ground_truth(series: Series, i: int, k: int, iters: int = 60) -> np.ndarray:
-    """Analytic displacement u_ik as a float64 array [2][H][W] (x, y planes)."""
+def ground_truth(series: Series, i: int, k: int, iters: int = 60, window=None) -> np.ndarray:
+    """Analytic displacement u_ik as a float64 array [2][H][W] (x, y planes),
+    on the pixels of ``window`` if given."""
     spec = series.spec
-    H, W = spec.height, spec.width
-    yy, xx = torch.meshgrid(torch.arange(H, dtype=torch.float64),
-                            torch.arange(W, dtype=torch.float64), indexing="ij")
+    yy, xx = _window_grid(spec, window, torch.device("cpu"))
     wix, wiy = _distortion(spec, series.theta[i], xx, yy)
     cx = xx - series.drift[i, 0] - wix + series.drift[k, 0]
     cy = yy - series.drift[i, 1] - wiy + series.drift[k, 1]
@@ -131,11 +140,10 @@ def ground_truth(series: Series, i: int, k: int, iters: int = 60) -> np.ndarray:
     return torch.stack([px - xx, py - yy]).numpy()
 
 
-def clean_frame(series: Series, k: int) -> np.ndarray:
+def clean_frame(series: Series, k: int, window=None) -> np.ndarray:
     """Noise-free frame k of a generated series as float64 [H][W] (for masks)."""
     spec = series.spec
-    yy, xx = torch.meshgrid(torch.arange(spec.height, dtype=torch.float64),
-                            torch.arange(spec.width, dtype=torch.float64), indexing="ij")
+    yy, xx = _window_grid(spec, window, torch.device("cpu"))
     wx, wy = _distortion(spec, series.theta[k], xx, yy)
     return lattice_image(spec, series.origin, xx - series.drift[k, 0] - wx,
                          yy - series.drift[k, 1] - wy).numpy()

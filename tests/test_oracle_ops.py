@@ -147,6 +147,45 @@ def test_restrict_constant_and_linear():
     np.testing.assert_allclose(reg.restrict_image(lin), 2.0 * (2 * cx + 0.5) + 0.5 * (2 * cy + 0.5))
 
 
+def test_frame_restriction_constant_linear_and_nyquist():
+    h, w = 16, 20
+    yy, xx = _grid(h, w)
+    assert np.array_equal(reg.restrict_frame(np.full((h, w), 3.5)), np.full((h // 2, w // 2), 3.5))
+    # symmetric about the block centre: a linear image is sampled at (2Y+1/2, 2X+1/2)
+    lin = 2.0 * xx + 0.5 * yy - 1.0
+    cy, cx = _grid(h // 2, w // 2)
+    want = 2.0 * (2 * cx + 0.5) + 0.5 * (2 * cy + 0.5) - 1.0
+    np.testing.assert_allclose(reg.restrict_frame(lin)[1:-1, 1:-1], want[1:-1, 1:-1], atol=1e-12)
+    # the highest frequency of the fine grid is removed (columns, rows, checkerboard)
+    for img in ((-1.0) ** xx, (-1.0) ** yy, (-1.0) ** (xx + yy)):
+        assert np.all(reg.restrict_frame(img.astype(float))[1:-1, 1:-1] == 0.0)
+
+
+@pytest.mark.parametrize("f", [1 / 16, 1 / 8, 1 / 6, 1 / 4, 1 / 3])
+def test_frame_restriction_frequency_response_is_cos5(f):
+    # closed form of the order-5 binomial: cos(2 pi f x + p) -> cos(pi f)^5 cos(2 pi f X' + p)
+    h, w = 12, 40
+    yy, xx = _grid(h, w)
+    img = np.cos(2 * np.pi * f * xx + 0.3)
+    cy, cx = _grid(h // 2, w // 2)
+    want = np.cos(np.pi * f) ** 5 * np.cos(2 * np.pi * f * (2 * cx + 0.5) + 0.3)
+    np.testing.assert_allclose(reg.restrict_frame(img)[:, 2:-2], want[:, 2:-2], atol=1e-13)
+
+
+def test_frame_restriction_matches_scipy_and_box_of_binomial5():
+    from scipy.ndimage import correlate1d
+    F = rng.standard_normal((18, 14))
+    wts = np.array([1, 5, 10, 10, 5, 1]) / 32.0
+    ref = correlate1d(correlate1d(F, wts, axis=0, mode="nearest"), wts, axis=1, mode="nearest")
+    np.testing.assert_allclose(reg.restrict_frame(F), ref[1::2, 1::2], atol=1e-14)
+    # [1 5 10 10 5 1]/32 = [1 1]/2 * [1 4 6 4 1]/16: the block mean of the
+    # 5-tap binomial smoothing (equal away from the clamped border)
+    b5 = correlate1d(correlate1d(F, np.array([1, 4, 6, 4, 1]) / 16.0, axis=0, mode="nearest"),
+                     np.array([1, 4, 6, 4, 1]) / 16.0, axis=1, mode="nearest")
+    np.testing.assert_allclose(reg.restrict_frame(F)[1:-1, 1:-1], reg.restrict_image(b5)[1:-1, 1:-1],
+                               atol=1e-14)
+
+
 def test_prolong_restrict_linear_field_interior():
     # a linear displacement survives restriction + prolongation in the interior
     h, w = 16, 20
@@ -209,6 +248,10 @@ def test_restriction_adjoints():
     G = rng.standard_normal((4, 3))
     assert np.sum(reg.restrict_image(F) * G) == pytest.approx(
         np.sum(F * autodiff.restrict_image_adjoint(G)), rel=1e-13)
+    F = rng.standard_normal((10, 8))
+    G = rng.standard_normal((5, 4))
+    assert np.sum(reg.restrict_frame(F) * G) == pytest.approx(
+        np.sum(F * autodiff.restrict_frame_adjoint(G, F.shape)), rel=1e-13)
 
 
 @pytest.mark.parametrize("levels", [1, 2, 3])

@@ -196,3 +196,86 @@ def test_flex_scan_agrees_with_sequential_recursion_on_clean_series():
     mask = _atom_mask(S, cfg.series, 0)
     dev = np.abs(phi0 - seq.phi0)[:, :, mask]
     assert dev.max() < 0.05
+
+
+# ------------------------------------------- storage precision of the oracle
+
+def test_float64_storage_keeps_unrounded_iterates():
+    # "f64" is plain float64: iterates are not float32 values; "f32" rounds
+    # every stored field (the mode the GPU is compared with bit for bit)
+    R, T = _lattice_pair((0.45, -0.35))
+    u0 = np.zeros((2, 24, 24))
+    a = reg.solve_level(R, T, u0, 0.5, 0.1, 12, True, 1e-5, storage="f32")
+    b = reg.solve_level(R, T, u0, 0.5, 0.1, 12, True, 1e-5, storage="f64")
+    assert np.array_equal(a.u, reg.f32(a.u))
+    assert not np.array_equal(b.u, reg.f32(b.u))
+    assert np.abs(a.u - b.u).max() < 1e-5
+    f = make_series(get_config(1, n_frames=1, height=32, width=32).series).frames[0].numpy().astype(np.float64)
+    p32, p64 = reg.pyramid(f, 3, "f32"), reg.pyramid(f, 3, "f64")
+    assert np.array_equal(p32[0], p64[0]) and np.array_equal(p32[2], reg.f32(p32[2]))
+    assert np.abs(p32[2] - p64[2]).max() < 1e-6 and not np.array_equal(p32[2], p64[2])
+
+
+# ------------------------- recovery along chains at the 512 and 1024 settings
+
+def _window_series(index, n, size):
+    cfg = get_config(index, n_frames=n)
+    H, W = cfg.series.height, cfg.series.width
+    win = ((H - size) // 2, (W - size) // 2, size, size)
+    return cfg, win, make_series(cfg.series, window=win)
+
+
+@pytest.mark.parametrize("index", [3, 5])
+def test_recovery_along_a_chain_keeps_every_prefix_registered(index):
+    """Recovery of known deformations through the scan (Section 2.3.2: each
+    frame registered to frame 0 from the composition of its neighbours).
+    Settings of the 1024 x 512x512 series (spacing 8, 3 levels, drift 8 px,
+    distortion 1.5 px, one extra-noise frame) and of the 4096 x 1024x1024
+    series (spacing 12, 4 levels, drift 16 px, distortion 2 px): 16 frames
+    on a central 128x128 window of the full-size frames (same drift walk and
+    distortion field; the coarsest grid keeps its 2 px and 1.5 px lattice
+    period).  Bounds on the interior (D + 2 px from the border), for every
+    prefix phi_{0,k}: rms <= 0.35 px, about twice the noise-limited accuracy
+    of a single registration (0.1-0.25 px measured), and max <= 2 px, half
+    of the half period of the 8 px lattice: a prefix that lost the lattice
+    anywhere would be off by a period there (8 or 12 px)."""
+    cfg, win, S = _window_series(index, 17, 128)
+    assert np.all(np.abs(np.diff(S.drift, axis=0)) <= cfg.series.spacing / 4)
+    res = run_scan(S.frames.numpy().astype(np.float64), cfg.solver, "seq",
+                   workers=min(8, len(__import__("os").sched_getaffinity(0))))
+    m = int(cfg.series.drift + 2)
+    moved = 0.0
+    for k in range(1, 17):
+        gt = ground_truth(S, 0, k, window=win)
+        d = (res.phi0[k - 1] - gt)[:, m:-m, m:-m]
+        rms, mx = np.sqrt(np.mean(d ** 2)), np.abs(d).max()
+        print(f"phi_0,{k}: rms {rms:.3f} px, max {mx:.2f} px, |drift| {np.abs(S.drift[k]).max():.1f} px")
+        assert rms <= 0.35 and mx <= 2.0, k
+        moved = max(moved, np.abs(gt).max())
+    # the chain reaches beyond half a lattice period from frame 0 (so it is
+    # the chaining, not one registration from the identity, that recovers it)
+    assert moved > cfg.series.spacing / 2
+
+
+def test_block_mean_pyramid_loses_the_lattice_where_the_binomial_keeps_it(monkeypatch):
+    """Why frames are coarsened by the binomial low-pass: on the 512x512
+    settings (3 levels: the coarsest grid samples the 8 px lattice with 2 px
+    per period), pair (7, 8) of the series registered from the identity on a
+    256x256 window.  With the 2x2 block mean the coarsest level pulls the
+    shift to its mirror image and the finer levels cannot recover it."""
+    cfg, win, S = _window_series(3, 9, 256)
+    win = (0, 0, 256, 256)
+    S = make_series(cfg.series, window=win)
+    fr = S.frames.numpy().astype(np.float64)
+    gt = ground_truth(S, 7, 8, window=win)
+
+    def run():
+        p = [reg.pyramid(fr[i], cfg.solver.levels) for i in (7, 8)]
+        u = reg.register(p[0], p[1], None, cfg.solver).u
+        return np.sqrt(np.mean((u - gt)[:, 10:-10, 10:-10] ** 2))
+
+    good = run()
+    monkeypatch.setattr(reg, "restrict_frame", reg.restrict_image)
+    bad = run()
+    print(f"binomial pyramid {good:.3f} px rms, block-mean pyramid {bad:.3f} px rms")
+    assert good <= 0.35 and bad >= 2.0
