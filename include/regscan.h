@@ -16,7 +16,9 @@
  *        + lambda * sum_{c in x,y} sum_x [ (u_c(x+e1) - u_c(x))^2 + (u_c(x+e2) - u_c(x))^2 ]
  * with forward differences taken only between pixels of the grid, T sampled
  * bilinearly with edge-clamped taps, minimised by u <- u - tau * dE/du on a
- * 2x2-box pyramid (coarse to fine).
+ * frame pyramid (coarse to fine) whose levels are binomial low-passes of the
+ * level below (see reg_pyramid); displacements pass between levels by half
+ * the 2x2 block mean (down) and bilinear prolongation (up).
  *
  * Arithmetic is double precision throughout; stored data (images,
  * displacements, gradients of the float32 entry points) are float32, each
@@ -126,8 +128,14 @@ const char* reg_last_error(void);
 /* Interface version (major * 100 + minor). */
 int reg_version(void);
 
-/* Frame pyramid (multilevel scheme, Section 2.3.1): level l+1 is the mean of
- * 2x2 blocks of level l.
+/* Frame pyramid (multilevel scheme, Section 2.3.1): pixel (Y, X) of level l+1
+ * is the separable order-5 binomial low-pass of level l centred on its 2x2
+ * block,
+ *   sum_{a,b=0..5} w_a w_b F_l[clamp(2Y+a-2)][clamp(2X+b-2)],
+ *   w = (1, 5, 10, 10, 5, 1) / 32, taps clamped to the level,
+ * each row summed over b first, then the rows over a, in double precision
+ * (a reading: the paper does not say how images are coarsened; the 2x2 block
+ * mean would pass lattice content that the coarser grid cannot resolve).
  *   frames  [N][H][W]             level 0, read only
  *   pyr     levels 1..L-1 back to back, level l is [N][H>>l][W>>l]
  *           (sum_{l=1}^{L-1} N*(H>>l)*(W>>l) floats); untouched if L == 1
@@ -140,7 +148,9 @@ int reg_pyramid(const float* frames, float* pyr, int N, int H, int W, int levels
 int reg_warp(const float* T, const float* u, float* out, int B, int H, int W, void* stream);
 int reg_warp_f64(const double* T, const double* u, double* out, int B, int H, int W, void* stream);
 
-/* Transpose of the warp with respect to T (scatter-add of the bilinear taps):
+/* Transpose of the warp with respect to T (scatter-add of the bilinear taps;
+ * the derivative of the deformed template T o phi of the Definition "Image
+ * registration problem" with respect to T, used by the backward pass):
  *   gT[b][tap(x)] += w_tap(x) * gout[b](x) for the four taps of x + u[b](x).
  *   gout [B][H][W], u [B][2][H][W], gT [B][H][W] accumulated (not cleared).
  * Uses atomic additions: the summation order, and so the last bits of gT,
@@ -148,7 +158,10 @@ int reg_warp_f64(const double* T, const double* u, double* out, int B, int H, in
 int reg_warp_adjoint(const float* gout, const float* u, float* gT, int B, int H, int W, void* stream);
 int reg_warp_adjoint_f64(const double* gout, const double* u, double* gT, int B, int H, int W, void* stream);
 
-/* Energy and gradient of the registration functional (one level):
+/* Energy and gradient of the registration functional (one level; the
+ * functional D(R, T o phi) of the Definition "Image registration problem",
+ * Section 2.3.1, in the dense form above, and its gradient, the direction of
+ * the gradient flow):
  *   E[b]      = E(u[b]) for reference R[b], template T[b]     (double, device)
  *   grad[b]   = dE/du at u[b] (exact away from integer sample positions;
  *               at an integer position the right-sided derivative), or NULL
@@ -161,7 +174,7 @@ int reg_energy_grad_f64(const double* R, const double* T, const double* u, doubl
                         double* E, double* grad, double* gnorm2, int B, int H, int W, void* stream);
 
 /* Differentiable warp + energy over a pyramid of `levels` levels:
- *   E[b] = sum_l E_l with I_a, I_b restricted by 2x2 block means and u by half
+ *   E[b] = sum_l E_l with I_a, I_b restricted as in reg_pyramid and u by half
  *   the 2x2 block mean, E_l the functional above with T = I_a^l, R = I_b^l.
  *   Ia, Ib [B][H][W]; u [B][2][H][W]; E [B] double.  Only the full-resolution
  *   inputs are read; coarser levels live in library workspace. */
@@ -187,12 +200,16 @@ int reg_pyramid_energy_backward_f64(const double* Ia, const double* u, const dou
  *   u_ij, u_jk, out [B][2][H][W]; out must not alias the inputs. */
 int reg_compose(const float* u_ij, const float* u_jk, float* out, int B, int H, int W, void* stream);
 
-/* Restriction to the next coarser grid: out[b] = scale * mean of 2x2 blocks.
- *   in [B][H][W], out [B][H/2][W/2]; H, W even.  scale = 1 for images, 0.5
- *   for displacement planes (pass each plane as its own batch item). */
+/* Restriction to the next coarser grid of the multilevel scheme (Section
+ * 2.3.1) as applied to displacements: out[b] = scale * mean of 2x2 blocks.
+ *   in [B][H][W], out [B][H/2][W/2]; H, W even.  scale = 0.5 restricts a
+ *   displacement plane (pass each plane as its own batch item): how the
+ *   initial guess reaches the coarsest level.  Frames are coarsened by
+ *   reg_pyramid instead. */
 int reg_restrict(const float* in, float* out, double scale, int B, int H, int W, void* stream);
 
-/* Prolongation of a displacement to the finer grid:
+/* Prolongation of a displacement to the finer grid (the coarse-to-fine step
+ * of the multilevel scheme, Section 2.3.1):
  *   uf[b](x) = 2 * uc[b]((x - 1/2)/2, (y - 1/2)/2) (bilinear, clamped).
  *   uc [B][2][Hf/2][Wf/2], uf [B][2][Hf][Wf]; Hf, Wf even. */
 int reg_prolong(const float* uc, float* uf, int B, int Hf, int Wf, void* stream);
@@ -218,7 +235,9 @@ int reg_solve_batch(const float* frames, int N, int H, int W,
                     const float* u0, float* u, int32_t* iters, int32_t* status, int B,
                     const reg_params_t* p, int mode, void* stream);
 
-/* Plan of the prefix scan over M elements (host only, no GPU use).
+/* Plan of the prefix scan over M elements (host only, no GPU use): the
+ * circuits of Section 2.1 (Table 1) and the reduce-then-scan of Section 4.1
+ * with the hierarchy of Section 4.2 (SCAN_HIER).
  *   algo        SCAN_*; global_algo is the global phase of SCAN_HIER
  *               (SCAN_SEQ..SCAN_BRENT_KUNG) and is ignored otherwise
  *   chunk       SCAN_HIER chunk length (<= 0 or >= M: a single chunk)
@@ -295,7 +314,8 @@ int scan_run_flex(const float* frames, int N, int H, int W, const reg_params_t* 
  *   taps (E = 1 with zero gradient when either image is constant);
  * gradient flow theta <- theta - tau (dE/dalpha / r^2, dE/dG_x, dE/dG_y) with
  * r^2 = ((W^2 - 1) + (H^2 - 1)) / 12 (the mean squared pixel distance from c),
- * per level the stopping rule of reg_solve_batch, on the box pyramid: the
+ * per level the stopping rule of reg_solve_batch, on the pyramid of
+ * reg_pyramid: the
  * initial guess enters the coarsest level with G / 2^(levels-1), each finer
  * level starts from the coarser result with G doubled, alpha is unchanged.
  * p->lambda is not used.

@@ -67,6 +67,8 @@ struct State {
   DevBuf rnodes, rtasks, rpart, rctrl, rflow;   // rigid operator: parameters, descriptors, sums, queue, DAG
   int rigid_blocks_per_cu = 0;
   double* h_E = nullptr;   // pinned host scalar for the plain path
+  int* h_abort = nullptr;  // pinned host copy of the sticky watchdog word
+  DevBuf abortw;           // sticky: a persistent launch of this call was aborted
   std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
   size_t events_used = 0;
   struct Graph {
@@ -98,6 +100,9 @@ int ensure_device() {
   if (nb < 1) return fail(REG_E_HIP, "persistent kernel cannot be resident");
   g.blocks_per_cu = nb;
   HIPCHK(hipHostMalloc((void**)&g.h_E, sizeof(double), hipHostMallocDefault));
+  HIPCHK(hipHostMalloc((void**)&g.h_abort, sizeof(int), hipHostMallocDefault));
+  if (hipMalloc(&g.abortw.p, 256) != hipSuccess) return fail(REG_E_NOMEM, "watchdog word");
+  g.abortw.n = 256;
   g.init = true;
   return REG_OK;
 }
@@ -269,6 +274,7 @@ int run_batched(SolveArgs a, const TaskDesc* d_tasks, int n, hipStream_t s, bool
   if (ev) HIPCHK(hipEventRecord(ev[0], s));
   HIPCHK(launch_persistent(a, L.grid, s));
   if (ev) HIPCHK(hipEventRecord(ev[1], s));
+  HIPCHK(launch_note_abort(a.ctrl, (int*)g.abortw.p, false, s));
   return REG_OK;
 }
 
@@ -302,6 +308,7 @@ int run_dataflow(SolveArgs a, const TaskDesc* d_tasks, int n, int* deps, const i
   if (ev) HIPCHK(hipEventRecord(ev[0], s));
   HIPCHK(launch_persistent(a, groups * gs, s));
   if (ev) HIPCHK(hipEventRecord(ev[1], s));
+  HIPCHK(launch_note_abort(a.ctrl, (int*)g.abortw.p, false, s));
   return REG_OK;
 }
 
@@ -365,6 +372,15 @@ int run_plain(SolveArgs a, const std::vector<TaskDesc>& tasks, const TaskDesc* d
     if (d.status) HIPCHK(hipMemcpyAsync(d.status, &status, sizeof(int32_t), hipMemcpyHostToDevice, s));
     HIPCHK(hipStreamSynchronize(s));   // host staging of iters/status must outlive the copies
   }
+  return REG_OK;
+}
+
+// Waits for the stream and reports a watchdog abort of any persistent launch
+// since the sticky word was last cleared.
+int check_abort(hipStream_t s, const char* what) {
+  HIPCHK(hipMemcpyAsync(g.h_abort, g.abortw.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (*g.h_abort) return fail(REG_E_HIP, "%s abandoned by the forward-progress watchdog", what);
   return REG_OK;
 }
 
@@ -513,7 +529,7 @@ int reg_pyramid(const float* frames, float* pyr, int N, int H, int W, int levels
   const float* src = frames;
   float* dst = pyr;
   for (int l = 1; l < levels; ++l) {
-    HIPCHK(launch_restrict(src, dst, 1.0, N, H >> (l - 1), W >> (l - 1), false, s));
+    HIPCHK(launch_restrict_frame(src, dst, N, H >> (l - 1), W >> (l - 1), false, s));
     src = dst;
     dst += (size_t)N * (H >> l) * (W >> l);
   }
@@ -610,8 +626,8 @@ static int pyramid_levels(const void* Ia, const void* u, const void* Ib, int lev
     p += n * es;
     void* v = p;
     p += 2 * n * es;
-    HIPCHK(launch_restrict(P.Ia[l - 1], a, 1.0, B, H >> (l - 1), W >> (l - 1), f64, s));
-    HIPCHK(launch_restrict(P.Ib[l - 1], b, 1.0, B, H >> (l - 1), W >> (l - 1), f64, s));
+    HIPCHK(launch_restrict_frame(P.Ia[l - 1], a, B, H >> (l - 1), W >> (l - 1), f64, s));
+    HIPCHK(launch_restrict_frame(P.Ib[l - 1], b, B, H >> (l - 1), W >> (l - 1), f64, s));
     HIPCHK(launch_restrict(P.u[l - 1], v, 0.5, 2 * B, H >> (l - 1), W >> (l - 1), f64, s));
     P.Ia[l] = a;
     P.Ib[l] = b;
@@ -691,10 +707,12 @@ static int pyr_backward_common(const void* Ia, const void* u, const void* Ib, do
   P.du[0] = du ? du : (void*)(scratch + 2 * n0 * es);
   for (int l = levels - 1; l >= 0; --l) {
     const bool top = l == levels - 1;
-    HIPCHK(launch_adjoint_init(top ? nullptr : P.dIa[l + 1], P.dIa[l], B, H >> l, W >> l, f64, s));
+    // dIa (scattered into) and dIb (added to) start from the transpose of
+    // the frame restriction applied to the coarser level's gradients
+    HIPCHK(launch_restrict_frame_adjoint(top ? nullptr : P.dIa[l + 1], P.dIa[l], B, H >> l, W >> l, f64, s));
+    if (!top) HIPCHK(launch_restrict_frame_adjoint(P.dIb[l + 1], P.dIb[l], B, H >> l, W >> l, f64, s));
     HIPCHK(launch_energy_backward_level(P.Ia[l], P.u[l], P.Ib[l], lam, gE, P.dIa[l], P.du[l], P.dIb[l],
-                                        top ? nullptr : P.du[l + 1], top ? nullptr : P.dIb[l + 1], B, H >> l,
-                                        W >> l, f64, s));
+                                        top ? nullptr : P.du[l + 1], !top, B, H >> l, W >> l, f64, s));
   }
   return REG_OK;
 }
@@ -779,8 +797,10 @@ int reg_solve_batch(const float* frames, int N, int H, int W, const int32_t* ref
   }
   TRY(upload_tasks(g.tasks, tasks, s));
   g.events_used = 0;
-  if (mode != REG_PLAIN) return run_batched(a, (const TaskDesc*)g.tasks.p, B, s, true);
-  return run_plain(a, tasks, (const TaskDesc*)g.tasks.p, s);
+  if (mode == REG_PLAIN) return run_plain(a, tasks, (const TaskDesc*)g.tasks.p, s);
+  HIPCHK(launch_note_abort((const int*)g.abortw.p, (int*)g.abortw.p, true, s));
+  TRY(run_batched(a, (const TaskDesc*)g.tasks.p, B, s, true));
+  return check_abort(s, "the batch");
 }
 
 int scan_plan(int M, int algo, int chunk, int global_algo, scan_op_t* ops, int cap, int* n_ops, int* n_levels) {
@@ -910,10 +930,10 @@ int scan_run(const float* frames, int N, int H, int W, const reg_params_t* p, in
   }
   const bool use_graph = (flags & SCAN_F_GRAPH) && mode != REG_PLAIN;
   char keybuf[512];
-  snprintf(keybuf, sizeof keybuf, "%p %p %p %p %p %d %d %d %d %d %d %.17g %.17g %.17g %d %d %d %d %d %d",
+  snprintf(keybuf, sizeof keybuf, "%p %p %p %p %p %d %d %d %d %d %d %.17g %.17g %.17g %d %d %d %d %d %d %d",
            (const void*)frames, (void*)phi0, (void*)pair, (void*)it_out, (void*)st_out, N, H, W, p->levels,
            p->max_iter, p->fixed_iter, p->tau, p->lambda, p->rel_tol, algo, chunk, global_algo, mode,
-           g.tile_rows, g.max_group);
+           g.tile_rows, g.max_group, (int)g.resident);
   const std::string key(keybuf);
   if (use_graph) {
     // graphs whose workspace has moved can never be replayed: free them
@@ -975,6 +995,7 @@ int scan_run(const float* frames, int N, int H, int W, const reg_params_t* p, in
 
   // every launch of the run; graph capture records exactly these
   auto enqueue = [&](hipStream_t st, const TaskDesc* d_tasks, int* dflow, bool timed) -> int {
+    if (mode != REG_PLAIN) HIPCHK(launch_note_abort((const int*)g.abortw.p, (int*)g.abortw.p, true, st));
     Pyr P;
     TRY(build_pyramid(frames, N, H, W, L, P, st));
     SolveArgs a = base_args(P, H, W, p);
@@ -1005,6 +1026,7 @@ int scan_run(const float* frames, int N, int H, int W, const reg_params_t* p, in
 
   g.events_used = 0;
   TRY(enqueue(s, (const TaskDesc*)g.tasks.p, (int*)g.flow.p, true));
+  if (mode != REG_PLAIN) TRY(check_abort(s, "the scan"));
   if (!use_graph) return REG_OK;
 
   // capture the same launches into a graph that owns copies of the descriptors
@@ -1783,7 +1805,8 @@ void reg_release(void) {
   if (!g.init) return;
   (void)hipDeviceSynchronize();
   for (DevBuf* b : {&g.pyr, &g.slots, &g.part, &g.ctrl, &g.tasks, &g.nodes, &g.upair, &g.iters, &g.status,
-                    &g.misc, &g.lvl, &g.flow, &g.mock, &g.flexw, &g.flexn, &g.flext, &g.flexf}) {
+                    &g.misc, &g.lvl, &g.flow, &g.mock, &g.flexw, &g.flexn, &g.flext, &g.flexf, &g.rnodes,
+                    &g.rtasks, &g.rpart, &g.rctrl, &g.rflow}) {
     if (b->p) (void)hipFree(b->p);
     b->p = nullptr;
     b->n = 0;

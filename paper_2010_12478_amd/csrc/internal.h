@@ -141,13 +141,17 @@ hipError_t launch_mock_phase3(const MockArgs& a, int workers, const int2* seg, c
 hipError_t launch_mock_gather(const int2* nodes, const int* final_node, int2* out, int n, hipStream_t s);
 
 // kernels.hip
+// out = scale * 2x2 block mean of in (the restriction of displacements)
 hipError_t launch_restrict(const void* in, void* out, double scale, int B, int H, int W, bool f64, hipStream_t s);
+// out = order-5 binomial frame restriction of in; its transpose (H x W is the fine size)
+hipError_t launch_restrict_frame(const void* in, void* out, int B, int H, int W, bool f64, hipStream_t s);
+hipError_t launch_restrict_frame_adjoint(const void* dC, void* dF, int B, int H, int W, bool f64, hipStream_t s);
 // Padded pyramid level (see SolveArgs): dst holds N frames of (h + 2) rows of
 // `pitch` floats, pixel (0, 0) at dst + pitch + kPadLeft, every frame
 // fstride = (h + 2) * pitch floats apart; rows -1 .. h and columns -1 .. w
 // hold the nearest pixel's value.  src == level 0: frames [N][h][w]
 // (copied); otherwise the padded level below (sp = its pitch, sfs = its
-// frame stride, pointer at its pixel (0, 0)), restricted by 2x2 block means.
+// frame stride, pointer at its pixel (0, 0)) under the frame restriction.
 constexpr int kPadLeft = 32;   // columns before pixel 0 (keeps rows 128-byte aligned)
 hipError_t launch_pad_level(const float* src, int sp, size_t sfs, bool copy, float* dst, int pitch, int N, int h,
                             int w, hipStream_t s);
@@ -160,9 +164,8 @@ hipError_t launch_energy_grad(const void* R, const void* T, const void* u, doubl
                               double* part, bool f64, hipStream_t s);
 hipError_t launch_energy_backward_level(const void* Ia, const void* u, const void* Ib, double lam,
                                         const double* gE, void* dIa, void* du, void* dIb,
-                                        const void* du_c, const void* dIb_c, int B, int h, int w,
+                                        const void* du_c, bool carry, int B, int h, int w,
                                         bool f64, hipStream_t s);
-hipError_t launch_adjoint_init(const void* dIa_c, void* dIa, int B, int h, int w, bool f64, hipStream_t s);
 hipError_t launch_add_energy(const double* Ein, double* Eacc, int B, int first, hipStream_t s);
 hipError_t launch_synth_frames(float* out, int F, int H, int W, hipStream_t s);
 
@@ -170,6 +173,8 @@ hipError_t launch_synth_frames(float* out, int F, int H, int W, hipStream_t s);
 const void* persistent_kernel();
 hipError_t launch_persistent(const SolveArgs& a, int grid, hipStream_t s);
 hipError_t launch_reset_ctrl(int* ctrl, int n_ints, hipStream_t s);
+// *sticky |= (ctrl[1] != 0) after a persistent launch; clear: *sticky = 0
+hipError_t launch_note_abort(const int* ctrl, int* sticky, bool clear, hipStream_t s);
 hipError_t launch_reset_tasks(int* ctrl, int n_ints, const TaskDesc* tasks, int n_tasks, hipStream_t s);
 // dataflow state: deps = deps0, ready = ready0, ctrl[3] (tail) = n_ready0
 hipError_t launch_reset_dataflow(int* deps, const int* deps0, int* ready, const int* ready0, int n_tasks,

@@ -31,10 +31,108 @@ __global__ void __launch_bounds__(kEW) k_restrict(const S* __restrict__ in, S* _
   }
 }
 
+// Per-axis weights of the frame restriction: the binomial coefficients of
+// (1 + z)^5 over 32 (exact binary fractions; a product with a float32 tap is
+// exact in float64).
+constexpr double kBinom6[6] = {1.0 / 32, 5.0 / 32, 10.0 / 32, 10.0 / 32, 5.0 / 32, 1.0 / 32};
+
+// Coarse pixel (Y, X) of the frame restriction of an h2 x w2 level `src`
+// (row pitch sp): the separable order-5 binomial low-pass centred on the
+// 2x2 block (2Y + 1/2, 2X + 1/2),
+//   sum_{a=0..5} w_a (sum_{b=0..5} w_b src[clamp(2Y+a-2)][clamp(2X+b-2)]),
+// each row's sum in increasing b, then the weighted rows in increasing a,
+// one rounded float64 operation each (no contraction).  It removes the
+// lattice content a coarser grid cannot represent (an atom lattice of two
+// coarse pixels per period or less would otherwise come through aliased or
+// sign-ambiguous) instead of passing 71% of it like the 2x2 block mean.
+template <typename S>
+__device__ __forceinline__ double binom6_pixel(const S* __restrict__ src, int sp, int h2, int w2, int Y, int X) {
+#pragma clang fp contract(off)
+  int xo[6];
+#pragma unroll
+  for (int b = 0; b < 6; ++b) xo[b] = clampi(2 * X + b - 2, 0, w2 - 1);
+  double acc = 0.0;
+#pragma unroll
+  for (int a = 0; a < 6; ++a) {
+    const S* r = src + (size_t)clampi(2 * Y + a - 2, 0, h2 - 1) * sp;
+    double row = kBinom6[0] * (double)r[xo[0]];
+#pragma unroll
+    for (int b = 1; b < 6; ++b) row = row + kBinom6[b] * (double)r[xo[b]];
+    acc = a == 0 ? kBinom6[0] * row : acc + kBinom6[a] * row;
+  }
+  return acc;
+}
+
+// out[b] = frame restriction of in[b] (H x W -> H/2 x W/2)
+template <typename S>
+__global__ void __launch_bounds__(kEW) k_restrict_frame(const S* __restrict__ in, S* __restrict__ out, int B,
+                                                        int H, int W) {
+  const int h = H >> 1, w = W >> 1;
+  const size_t n = (size_t)B * h * w;
+  for (size_t t = blockIdx.x * (size_t)kEW + threadIdx.x; t < n; t += (size_t)gridDim.x * kEW) {
+    const size_t b = t / ((size_t)h * w);
+    const int r = (int)(t - b * h * w);
+    const int Y = r / w, X = r - Y * w;
+    out[t] = (S)binom6_pixel(in + b * H * W, W, H, W, Y, X);
+  }
+}
+
+// Weights with which fine row y (of n2 = 2 n) enters coarse rows Y0 .. Y0 + 3
+// of the frame restriction: w[i] = sum of kBinom6[a] over the taps a of
+// coarse row Y0 + i whose clamped index is y (zero past the last row).
+__device__ __forceinline__ int binom6_adjoint_rows(int y, int n2, double w[4]) {
+  const int n = n2 >> 1;
+  const int Y0 = max((y - 3) >> 1, 0);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int Y = Y0 + i;
+    double s = 0.0;
+    if (Y < n) {
+#pragma unroll
+      for (int a = 0; a < 6; ++a)
+        if (clampi(2 * Y + a - 2, 0, n2 - 1) == y) s += kBinom6[a];
+    }
+    w[i] = s;
+  }
+  return Y0;
+}
+
+// dF[b] = transpose of the frame restriction applied to dC[b]
+// (H/2 x W/2 -> H x W), gathered per fine pixel; dC == nullptr: zeros.
+template <typename S>
+__global__ void __launch_bounds__(kEW) k_restrict_frame_adjoint(const S* __restrict__ dC, S* __restrict__ dF,
+                                                                int B, int H, int W) {
+  const int h = H >> 1, w = W >> 1;
+  const size_t HW = (size_t)H * W, n = (size_t)B * HW;
+  for (size_t t = blockIdx.x * (size_t)kEW + threadIdx.x; t < n; t += (size_t)gridDim.x * kEW) {
+    const size_t b = t / HW;
+    if (!dC) {
+      dF[t] = S(0);
+      continue;
+    }
+    const int r = (int)(t - b * HW);
+    const int y = r / W, x = r - y * W;
+    double wy[4], wx[4];
+    const int Y0 = binom6_adjoint_rows(y, H, wy);
+    const int X0 = binom6_adjoint_rows(x, W, wx);
+    const S* c = dC + b * (size_t)h * w;
+    double acc = 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (wy[i] == 0.0) continue;
+      double row = 0.0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (wx[j] != 0.0) row += wx[j] * (double)c[(size_t)(Y0 + i) * w + X0 + j];
+      acc += wy[i] * row;
+    }
+    dF[t] = (S)acc;
+  }
+}
+
 // Padded pyramid level: element (Y, X), Y in [-1, h], X in [-1, w], of frame
 // f holds pixel (clamp(Y), clamp(X)) of the level: a copy of the frame
-// (COPY) or the 2x2 block mean of the padded level below, in the order and
-// precision of k_restrict.
+// (COPY) or the frame restriction (binom6_pixel) of the level below.
 template <bool COPY>
 __global__ void __launch_bounds__(kEW) k_pad_level(const float* __restrict__ src, int sp, size_t sfs,
                                                    float* __restrict__ dst, int pitch, int N, int h, int w) {
@@ -47,13 +145,10 @@ __global__ void __launch_bounds__(kEW) k_pad_level(const float* __restrict__ src
     const int Y = r / wp - 1, X = r - (Y + 1) * wp - 1;
     const int yc = clampi(Y, 0, h - 1), xc = clampi(X, 0, w - 1);
     float v;
-    if (COPY) {
+    if (COPY)
       v = src[f * h * w + (size_t)yc * w + xc];
-    } else {
-      const float* q = src + f * sfs + (size_t)(2 * yc) * sp + 2 * xc;
-      const double sum = (((double)q[0] + (double)q[1]) + (double)q[sp]) + (double)q[sp + 1];
-      v = (float)(0.25 * sum);
-    }
+    else
+      v = (float)binom6_pixel(src + f * sfs, sp, 2 * h, 2 * w, yc, xc);
     dst[f * fstride + (size_t)(Y + 1) * pitch + kPadLeft + X] = v;
   }
 }
@@ -306,13 +401,14 @@ __global__ void __launch_bounds__(kWave) k_sum_tiles(const double* part, const d
 // One level of the backward pass.  Per pixel x of item b:
 //   r = Ia(x + u(x)) - Ib(x), g = dE_l/du(x)
 //   du(x)  = gE g(x)     + 1/8 du_c(parent)     (adjoint of half the block mean)
-//   dIb(x) = -2 r gE     + 1/4 dIb_c(parent)    (adjoint of the block mean)
+//   dIb(x) = -2 r gE     (+ dIb(x) if carry: it holds the adjoint of the
+//                          frame restriction applied to the coarser dIb)
 //   dIa   += 2 r gE * bilinear weights at the taps (dIa pre-initialised)
 template <typename S>
 __global__ void __launch_bounds__(kEW) k_energy_backward(const S* __restrict__ Ia, const S* __restrict__ u,
                                                          const S* __restrict__ Ib, double lam,
                                                          const double* __restrict__ gE, S* dIa, S* du,
-                                                         S* dIb, const S* du_c, const S* dIb_c,
+                                                         S* dIb, const S* du_c, bool carry,
                                                          int B, int H, int W) {
   const size_t HW = (size_t)H * W;
   const int hc = H >> 1, wc = W >> 1;
@@ -384,7 +480,7 @@ __global__ void __launch_bounds__(kEW) k_energy_backward(const S* __restrict__ I
         gx += 0.125 * (double)du_c[pc];
         gy += 0.125 * (double)du_c[pc + HWc];
       }
-      if (dIb_c) gb += 0.25 * (double)dIb_c[(size_t)b * HWc + (size_t)(y >> 1) * wc + (x >> 1)];
+      if (carry) gb += (double)dIb[q];
       du[(size_t)b * 2 * HW + r] = (S)gx;
       du[(size_t)b * 2 * HW + HW + r] = (S)gy;
       dIb[q] = (S)gb;
@@ -397,24 +493,6 @@ __global__ void __launch_bounds__(kEW) k_energy_backward(const S* __restrict__ I
 #pragma unroll
     for (int k = 0; k < kBackRows; ++k) sc.pixel(db, H, W, col && y0 + k < H, x, y0 + k, sx[k], sy[k], sv[k]);
     sc.finish(db, W);
-  }
-}
-
-template <typename S>
-__global__ void __launch_bounds__(kEW) k_adjoint_init(const S* __restrict__ dIa_c, S* __restrict__ dIa,
-                                                      int B, int H, int W) {
-  const size_t HW = (size_t)H * W, n = (size_t)B * HW;
-  const int wc = W >> 1;
-  const size_t HWc = (size_t)(H >> 1) * wc;
-  for (size_t t = blockIdx.x * (size_t)kEW + threadIdx.x; t < n; t += (size_t)gridDim.x * kEW) {
-    if (!dIa_c) {
-      dIa[t] = S(0);
-    } else {
-      const size_t b = t / HW;
-      const int r = (int)(t - b * HW);
-      const int y = r / W, x = r - y * W;
-      dIa[t] = (S)(0.25 * (double)dIa_c[b * HWc + (size_t)(y >> 1) * wc + (x >> 1)]);
-    }
   }
 }
 
@@ -449,6 +527,30 @@ hipError_t launch_restrict(const void* in, void* out, double scale, int B, int H
   else
     hipLaunchKernelGGL(k_restrict<float>, dim3(ew_blocks(n)), dim3(kEW), 0, s, (const float*)in,
                        (float*)out, scale, B, H, W);
+  return hipGetLastError();
+}
+
+hipError_t launch_restrict_frame(const void* in, void* out, int B, int H, int W, bool f64, hipStream_t s) {
+  const size_t n = (size_t)B * (H / 2) * (W / 2);
+  if (n == 0) return hipSuccess;
+  if (f64)
+    hipLaunchKernelGGL(k_restrict_frame<double>, dim3(ew_blocks(n)), dim3(kEW), 0, s, (const double*)in,
+                       (double*)out, B, H, W);
+  else
+    hipLaunchKernelGGL(k_restrict_frame<float>, dim3(ew_blocks(n)), dim3(kEW), 0, s, (const float*)in,
+                       (float*)out, B, H, W);
+  return hipGetLastError();
+}
+
+hipError_t launch_restrict_frame_adjoint(const void* dC, void* dF, int B, int H, int W, bool f64, hipStream_t s) {
+  const size_t n = (size_t)B * H * W;
+  if (n == 0) return hipSuccess;
+  if (f64)
+    hipLaunchKernelGGL(k_restrict_frame_adjoint<double>, dim3(ew_blocks(n)), dim3(kEW), 0, s, (const double*)dC,
+                       (double*)dF, B, H, W);
+  else
+    hipLaunchKernelGGL(k_restrict_frame_adjoint<float>, dim3(ew_blocks(n)), dim3(kEW), 0, s, (const float*)dC,
+                       (float*)dF, B, H, W);
   return hipGetLastError();
 }
 
@@ -545,29 +647,17 @@ hipError_t launch_energy_grad(const void* R, const void* T, const void* u, doubl
 
 hipError_t launch_energy_backward_level(const void* Ia, const void* u, const void* Ib, double lam,
                                         const double* gE, void* dIa, void* du, void* dIb, const void* du_c,
-                                        const void* dIb_c, int B, int h, int w, bool f64, hipStream_t s) {
+                                        bool carry, int B, int h, int w, bool f64, hipStream_t s) {
   const size_t n = (size_t)B * h * w;
   if (n == 0) return hipSuccess;
   if (f64)
     hipLaunchKernelGGL(k_energy_backward<double>, adjoint_grid(B, h, w, kBackRows), dim3(kEW), 0, s, (const double*)Ia,
                        (const double*)u, (const double*)Ib, lam, gE, (double*)dIa, (double*)du, (double*)dIb,
-                       (const double*)du_c, (const double*)dIb_c, B, h, w);
+                       (const double*)du_c, carry, B, h, w);
   else
     hipLaunchKernelGGL(k_energy_backward<float>, adjoint_grid(B, h, w, kBackRows), dim3(kEW), 0, s, (const float*)Ia,
                        (const float*)u, (const float*)Ib, lam, gE, (float*)dIa, (float*)du,
-                       (float*)dIb, (const float*)du_c, (const float*)dIb_c, B, h, w);
-  return hipGetLastError();
-}
-
-hipError_t launch_adjoint_init(const void* dIa_c, void* dIa, int B, int h, int w, bool f64, hipStream_t s) {
-  const size_t n = (size_t)B * h * w;
-  if (n == 0) return hipSuccess;
-  if (f64)
-    hipLaunchKernelGGL(k_adjoint_init<double>, dim3(ew_blocks(n)), dim3(kEW), 0, s, (const double*)dIa_c,
-                       (double*)dIa, B, h, w);
-  else
-    hipLaunchKernelGGL(k_adjoint_init<float>, dim3(ew_blocks(n)), dim3(kEW), 0, s, (const float*)dIa_c,
-                       (float*)dIa, B, h, w);
+                       (float*)dIb, (const float*)du_c, carry, B, h, w);
   return hipGetLastError();
 }
 

@@ -1000,6 +1000,16 @@ hipError_t launch_rigid(const RigidArgs& a, int grid, hipStream_t s) {
   return hipGetLastError();
 }
 
+// *sticky |= the abort word of a finished persistent launch (clear: *sticky = 0)
+__global__ void k_note_abort(const int* ctrl, int* sticky, int clear) {
+  if (threadIdx.x == 0) *sticky = clear ? 0 : (*sticky | (ctrl[1] != 0));
+}
+
+hipError_t launch_note_abort(const int* ctrl, int* sticky, bool clear, hipStream_t s) {
+  hipLaunchKernelGGL(k_note_abort, dim3(1), dim3(64), 0, s, ctrl, sticky, clear ? 1 : 0);
+  return hipGetLastError();
+}
+
 hipError_t launch_reset_ctrl(int* ctrl, int n_ints, hipStream_t s) {
   hipLaunchKernelGGL(k_reset, dim3(grid_for((size_t)n_ints)), dim3(256), 0, s, ctrl, n_ints,
                      (const TaskDesc*)nullptr, 0);

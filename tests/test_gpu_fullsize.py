@@ -14,11 +14,12 @@ batched mode with the library defaults, and then sampled:
 * iteration counts of those registrations, which must agree exactly.
 
 Properties that hold at any size are checked on every output: all fields are
-finite and no registration is flagged non-finite or aborted.  The distance of
-sampled prefixes phi_{0,k} from the generator's known deformation is printed
-(a report, not a bound: with the frozen step and the 200-iteration cap some
-registrations of the noisier series stop a few pixels from it, and the
-oracle stops at the same place).
+finite and no registration is flagged non-finite or aborted.  Recovery of the
+generator's known deformation (Section 2.3.2: each frame registered to frame 0
+through the chain of its neighbours) is bounded on prefixes phi_{0,k} spread
+over the whole series, on the interior D + 2 px from the border: rms <= 0.35
+px, the bound of the oracle's recovery pins, and max <= 3 px, below half the
+8 px lattice period (a prefix that lost the lattice would be a period off).
 """
 import multiprocessing as mp
 from concurrent.futures import ProcessPoolExecutor
@@ -30,13 +31,15 @@ import torch
 from oracle import autodiff as oad
 from oracle import plans as oplans
 from oracle import registration as oreg
-from synth import clean_frame, get_config, ground_truth, make_series
+from synth import get_config, ground_truth, make_series
 
 from _helpers import announce, host
 
 pytestmark = pytest.mark.gpu
 
 TOL_PX = 1e-3
+GT_RMS_PX = 0.35
+GT_MAX_PX = 3.0
 
 
 @pytest.fixture(scope="module")
@@ -76,7 +79,9 @@ def _series_case(rs, index, pair_ks, n_prefix, gt_ks):
     iters = host(iters_d)
     assert (status & 6 == 0).all(), "non-finite or aborted registrations"
     assert bool(torch.isfinite(phi0_d).all()) and bool(torch.isfinite(u_pair_d).all())
-    print(f"{cfg.name}: {int((status & 1).sum())} of {len(status)} registrations stopped at the cap")
+    print(f"{cfg.name}: {int((status & 1).sum())} of {len(status)} registrations stopped at the cap; "
+          f"per level (finest first) {list((iters >= p.max_iter).sum(axis=0))} capped, "
+          f"mean iterations {[round(float(v), 1) for v in iters.mean(axis=0)]}")
     ops, _ = oplans.make_plan(M, cfg.algo, cfg.chunk, cfg.global_algo)
     prefix_op = {}
     for k in range(2, n_prefix + 1):
@@ -101,28 +106,29 @@ def _series_case(rs, index, pair_ks, n_prefix, gt_ks):
         _compare(f"{cfg.name} phi_0,{k}", host(phi0_d[k - 1]).astype(np.float64), y, iters[prefix_op[k]], it)
 
     S_host = type(S)(S.spec, None, S.drift, S.theta, S.origin, S.noisy)
-    clean = clean_frame(S_host, 0)
     b = int(spec.drift + 2)
-    mask = np.zeros(clean.shape, bool)
-    mask[b:-b, b:-b] = True
-    mask &= clean >= np.exp(-2.0)
+    worst = []
     for k in gt_ks:
-        e = (host(phi0_d[k - 1]) - ground_truth(S_host, 0, k))[:, mask]
-        print(f"{cfg.name} phi_0,{k} vs generator (report): rms {float(np.sqrt((e ** 2).mean())):.3f} px, "
+        e = (host(phi0_d[k - 1]) - ground_truth(S_host, 0, k))[:, b:-b, b:-b]
+        rms, mx = float(np.sqrt((e ** 2).mean())), float(np.abs(e).max())
+        worst.append((rms, mx, k))
+        print(f"{cfg.name} phi_0,{k} vs generator: rms {rms:.3f} px, max {mx:.2f} px, "
               f"drift {np.abs(S.drift[k] - S.drift[0]).max():.1f} px")
+    for rms, mx, k in worst:
+        assert rms <= GT_RMS_PX and mx <= GT_MAX_PX, f"phi_0,{k} lost the generator's deformation"
 
 
 def test_full_size_series1024_512x512(rs):
     """1024 frames 512x512, 3 levels, 10% of frames with extra noise,
     hierarchical plan (chunks of 32, Ladner-Fischer global phase)."""
-    _series_case(rs, 3, pair_ks=[511, 1023], n_prefix=3, gt_ks=[2, 64, 512, 1023])
+    _series_case(rs, 3, pair_ks=[511, 1023], n_prefix=3, gt_ks=list(range(1, 1024, 64)) + [1023])
 
 
 @pytest.mark.timeout(900)
 def test_full_size_series4096_1024x1024(rs):
     """4096 frames 1024x1024, 4 levels, lattice spacing 12 px, drift up to
     16 px, hierarchical plan (chunks of 64, Ladner-Fischer global phase)."""
-    _series_case(rs, 5, pair_ks=[2048, 4095], n_prefix=2, gt_ks=[2, 100, 1000, 4095])
+    _series_case(rs, 5, pair_ks=[2048, 4095], n_prefix=2, gt_ks=list(range(1, 4096, 256)) + [4095])
 
 
 def test_full_size_autograd_64_pairs_512x512(rs):
