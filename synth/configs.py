@@ -27,6 +27,19 @@ TAU = 0.5
 LAMBDA = 0.1
 BASE_SEED = 1410
 
+# Relative-decrease tolerance of the 512x512 and 1024x1024 series, whose
+# stopping rule is not stated (the 256x256 series states 1e-5).  At 1e-5 the
+# finest level keeps fitting the noise long after the deformation is found:
+# on the 1024x1024 settings a pairwise registration reaches the finest level
+# 0.112 px rms from the generator's deformation and ends 0.177 px away after
+# 178 more iterations, the energy still falling.  At 1e-3 the chained
+# prefixes of 16-frame windows of both series end as close or closer to the
+# generator (mean rms 0.118 against 0.130 px at 512x512, 0.149 against
+# 0.158 px at 1024x1024) with 2.2-2.8 times fewer pixel passes, and a
+# coarsest level whose lattice the pyramid has suppressed stops after a few
+# iterations instead of drifting to the cap.
+REL_TOL_LARGE = 1e-3
+
 # Rigid normalized-cross-correlation operator: gradient-flow step in the metric
 # diag(r^2, 1, 1) (angle scaled by the mean squared pixel radius r^2).  On the
 # lattice series a step of 1.0 recovers a (2 deg, 1.3 px, -0.7 px) motion to
@@ -91,7 +104,7 @@ CONFIGS: dict[int, Config] = {
               SeriesSpec(1024, 512, 512, spacing=8.0, drift=8.0, distort=1.5,
                          noise=0.1, extra_noise_frac=0.1, extra_noise=0.3,
                          seed=BASE_SEED + 3),
-              SolverParams(levels=3, max_iter=200),
+              SolverParams(levels=3, max_iter=200, rel_tol=REL_TOL_LARGE),
               algo="hier", chunk=32, global_algo="lf"),
     4: Config(4, "pairs64-512x512-autograd",
               SeriesSpec(65, 512, 512, spacing=8.0, drift=8.0, distort=1.5,
@@ -102,7 +115,7 @@ CONFIGS: dict[int, Config] = {
     5: Config(5, "series4096-1024x1024-hier",
               SeriesSpec(4096, 1024, 1024, spacing=12.0, drift=16.0,
                          distort=2.0, noise=0.1, seed=BASE_SEED + 5),
-              SolverParams(levels=4, max_iter=200),
+              SolverParams(levels=4, max_iter=200, rel_tol=REL_TOL_LARGE),
               algo="hier", chunk=64, global_algo="lf"),
 }
 
