@@ -173,6 +173,20 @@ int reg_energy_grad(const float* R, const float* T, const float* u, double lambd
 int reg_energy_grad_f64(const double* R, const double* T, const double* u, double lambda,
                         double* E, double* grad, double* gnorm2, int B, int H, int W, void* stream);
 
+/* reg_energy_grad for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid hipMalloc): the same
+ * kernels and results (bitwise, at the same tile height), but the per-tile
+ * partial sums live in a fixed 2 MiB device array that every GPU holds for
+ * the life of the process, instead of library workspace; no hipMalloc,
+ * hipFree or other allocation happens in the call.
+ * Limit: (gnorm2 ? 2 : 1) * B * tiles <= 262144, tiles = ceil(W / 64) *
+ * ceil(H / tile_rows) (tile_rows: reg_set_tuning, default 64; e.g. B <= 1024
+ * at 1024x1024 for the energy alone); larger calls return REG_E_INVALID
+ * before anything is enqueued.  Calls that overlap on one GPU (other
+ * streams or threads) share the array and race; serialise them. */
+int reg_energy_grad_noalloc(const float* R, const float* T, const float* u, double lambda,
+                            double* E, float* grad, double* gnorm2, int B, int H, int W, void* stream);
+
 /* Differentiable warp + energy over a pyramid of `levels` levels:
  *   E[b] = sum_l E_l with I_a, I_b restricted as in reg_pyramid and u by half
  *   the 2x2 block mean, E_l the functional above with T = I_a^l, R = I_b^l.

@@ -27,7 +27,7 @@ SCAN_F_GRAPH = 1
 
 EXPORTS = (
     "reg_last_error", "reg_version", "reg_pyramid", "reg_warp", "reg_warp_f64",
-    "reg_warp_adjoint", "reg_warp_adjoint_f64", "reg_energy_grad", "reg_energy_grad_f64",
+    "reg_warp_adjoint", "reg_warp_adjoint_f64", "reg_energy_grad", "reg_energy_grad_f64", "reg_energy_grad_noalloc",
     "reg_pyramid_energy", "reg_pyramid_energy_f64", "reg_pyramid_energy_backward",
     "reg_pyramid_energy_backward_f64", "reg_compose", "reg_restrict", "reg_prolong",
     "reg_solve_batch", "scan_plan", "scan_run", "reg_last_solve_timing", "reg_last_solve_launch_ms",
@@ -76,6 +76,7 @@ _SIGS = {
     "reg_warp_adjoint_f64": (_I, [_P, _P, _P, _I, _I, _I, _P]),
     "reg_energy_grad": (_I, [_P, _P, _P, _D, _P, _P, _P, _I, _I, _I, _P]),
     "reg_energy_grad_f64": (_I, [_P, _P, _P, _D, _P, _P, _P, _I, _I, _I, _P]),
+    "reg_energy_grad_noalloc": (_I, [_P, _P, _P, _D, _P, _P, _P, _I, _I, _I, _P]),
     "reg_pyramid_energy": (_I, [_P, _P, _P, _D, _I, _P, _I, _I, _I, _P]),
     "reg_pyramid_energy_f64": (_I, [_P, _P, _P, _D, _I, _P, _I, _I, _I, _P]),
     "reg_pyramid_energy_backward": (_I, [_P, _P, _P, _D, _I, _P, _P, _P, _P, _I, _I, _I, _P]),

@@ -93,6 +93,26 @@ def energy_grad(R, T, u, lam, want_grad=True, want_gnorm=False):
     return E, g, gn
 
 
+def energy_grad_noalloc(R, T, u, lam, want_grad=True, want_gnorm=False, E=None, grad=None, gnorm=None):
+    """energy_grad through the allocation-free entry point (float32 inputs;
+    the library allocates nothing; outputs may be passed in)."""
+    B, H, W = _bhw(R, "R")
+    for t, n in ((R, "R"), (T, "T"), (u, "u")):
+        _need(t, n)
+    if T.numel() != B * H * W or u.numel() != B * 2 * H * W:
+        raise ValueError("T must hold [B][H][W] and u [B][2][H][W]")
+    dev = R.device
+    if E is None:
+        E = torch.empty(B, dtype=torch.float64, device=dev)
+    if grad is None and want_grad:
+        grad = torch.empty((B, 2, H, W), dtype=torch.float32, device=dev)
+    if gnorm is None and want_gnorm:
+        gnorm = torch.empty(B, dtype=torch.float64, device=dev)
+    check(lib.reg_energy_grad_noalloc(_ptr(R), _ptr(T), _ptr(u), float(lam), _ptr(E), _ptr(grad), _ptr(gnorm),
+                                      B, H, W, _stream()))
+    return E, grad, gnorm
+
+
 def pyramid_energy(Ia, u, Ib, lam, levels=1):
     f64 = Ia.dtype == torch.float64
     dt = torch.float64 if f64 else torch.float32

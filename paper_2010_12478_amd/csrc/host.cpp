@@ -591,6 +591,58 @@ int reg_energy_grad(const float* R, const float* T, const float* u, double lambd
                     double* gnorm2, int B, int H, int W, void* stream) {
   return energy_common(R, T, u, lambda, E, grad, gnorm2, B, H, W, stream, false);
 }
+
+// Scratch of reg_energy_grad_noalloc: the per-tile partial sums (energies,
+// then squared gradient norms) that reg_energy_grad keeps in library
+// workspace.  Every GPU holds its own copy until the process ends; every
+// call on a GPU reuses it (calls that overlap on one GPU race).  The kernels
+// write every partial sum before it is read, so nothing needs clearing.
+// In host code `scratch` only stands for the symbol: its device address on
+// the current GPU comes from hipGetSymbolAddress (noalloc_scratch).
+constexpr size_t kNoallocSums = 262144;   // doubles: 2 MiB
+static __device__ __align__(256) double scratch[kNoallocSums];
+
+constexpr int kNoallocDevices = 64;
+double* g_scratch_addr[kNoallocDevices] = {};   // per device, set on the first call there
+
+// Device address of `scratch` on the current GPU (looked up once per GPU;
+// allocates nothing).
+static int noalloc_scratch(double** out) {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kNoallocDevices) return fail(REG_E_NODEVICE, "device %d beyond %d", dev, kNoallocDevices);
+  if (!g_scratch_addr[dev]) {
+    hipDeviceProp_t prop;
+    HIPCHK(hipGetDeviceProperties(&prop, dev));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+      return fail(REG_E_NODEVICE, "device %s is not gfx950 (this library is built for gfx950 only)",
+                  prop.gcnArchName);
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_scratch_addr[dev] = (double*)p;
+  }
+  *out = g_scratch_addr[dev];
+  return REG_OK;
+}
+
+int reg_energy_grad_noalloc(const float* R, const float* T, const float* u, double lambda, double* E,
+                            float* grad, double* gnorm2, int B, int H, int W, void* stream) {
+  std::lock_guard<std::recursive_mutex> lk(g_mu);
+  TRY(check_dims(B, H, W));
+  if (B == 0) return REG_OK;
+  if (!R || !T || !u || !E) return fail(REG_E_INVALID, "NULL pointer");
+  if (!(lambda >= 0.0) || !std::isfinite(lambda)) return fail(REG_E_INVALID, "lambda must be >= 0 and finite");
+  const int th = g.tile_rows;
+  const size_t sums = (size_t)(gnorm2 ? 2 : 1) * B * tiles_of(H, W, th);
+  if (sums > kNoallocSums)
+    return fail(REG_E_INVALID, "%zu tile sums (B = %d, %d tiles of %dx%d, %s) exceed the %zu of the allocation-free "
+                "scratch", sums, B, tiles_of(H, W, th), H, W, gnorm2 ? "energy and gradient norm" : "energy",
+                kNoallocSums);
+  double* part = nullptr;
+  TRY(noalloc_scratch(&part));
+  HIPCHK(launch_energy_grad(R, T, u, lambda, E, grad, gnorm2, B, H, W, th, part, false, (hipStream_t)stream));
+  return REG_OK;
+}
 int reg_energy_grad_f64(const double* R, const double* T, const double* u, double lambda, double* E,
                         double* grad, double* gnorm2, int B, int H, int W, void* stream) {
   return energy_common(R, T, u, lambda, E, grad, gnorm2, B, H, W, stream, true);
