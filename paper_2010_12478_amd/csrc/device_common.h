@@ -11,6 +11,7 @@ constexpr int kWave = 64;
 constexpr int kTileW = 64;      // a tile row is one wavefront wide
 constexpr int kMaxLevels = 8;
 constexpr int kRB = 2;          // rows per register batch in the sweep
+constexpr int kSweepTiles = 64; // tile sums per workgroup synchronisation in the solver's sweep
 constexpr int kMaxRPT = 16;     // rows per thread of a register-resident tile at most (tile height 64)
 
 __host__ __device__ inline int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }

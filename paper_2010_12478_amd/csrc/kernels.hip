@@ -366,7 +366,7 @@ template <typename S, int WRITE, bool GNORM>
 __global__ void __launch_bounds__(kWG) k_energy_tiles(const S* __restrict__ R, const S* __restrict__ T,
                                                       const S* __restrict__ u, double lam, S* grad,
                                                       double* part, double* gpart, int H, int W, int th) {
-  __shared__ double red[kWG / kWave];
+  __shared__ double red[sweep_red_doubles<true>(1)];
   const size_t HW = (size_t)H * W;
   const int b = blockIdx.y, nt = tiles_of(H, W, th);
   LevelView<S> L;

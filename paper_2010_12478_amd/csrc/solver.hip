@@ -273,6 +273,9 @@ __device__ __forceinline__ float* start_buffer(const SolveArgs& a, const TaskDes
 }
 
 // Runs one registration with the calling group.  Returns false on abort.
+// RES: levels that fit the group may run register-resident (otherwise every
+// level streams, and the resident code is not compiled in).
+template <bool RES>
 __device__ __forceinline__ bool run_task(const SolveArgs& a, const TaskDesc& d, Group& G, float* slot, double* part, int& par,
                          double* red, double* s_E, int* s_flag, float2* roll) {
   int* abort_flag = a.ctrl + 1;
@@ -326,7 +329,8 @@ __device__ __forceinline__ bool run_task(const SolveArgs& a, const TaskDesc& d, 
     V.lam = a.lam;
     const int th = a.thl[l];
     const int nt = tiles_of(h, w, th);
-    if (a.resident && w % kTileW == 0 && h % th == 0 && nt <= G.g && th <= 4 * kMaxRPT && (th & (th - 1)) == 0) {
+    if (RES && a.resident && w % kTileW == 0 && h % th == 0 && nt <= G.g && th <= 4 * kMaxRPT &&
+        (th & (th - 1)) == 0) {
       int it = 0;
       bool nf = false, ok = true;
       if (th == 4) ok = level_resident<1>(a, V, cur, bufB, slot, G, part, par, red, s_E, s_flag, roll, it, nf);
@@ -352,7 +356,7 @@ __device__ __forceinline__ bool run_task(const SolveArgs& a, const TaskDesc& d, 
       V.u = cur;
       V.out = other;
       double* pp = part + (size_t)par * a.max_tiles;
-      sweep_tiles<float, SW_UPDATE, false, true>(V, G.member, G.g, th, red, pp, nullptr);
+      sweep_tiles<float, SW_UPDATE, false, true, kRB, kSweepTiles>(V, G.member, G.g, th, red, pp, nullptr);
       if (!group_sync(G, abort_flag, a.spin_limit, s_flag)) return false;
       if (threadIdx.x < kWave) {
         const double E = wave_sum_array(pp, nt, threadIdx.x);
@@ -524,14 +528,18 @@ __device__ int flex_next(const SolveArgs& a, Group& G, FlexState& F, TaskDesc& d
 }
 
 // FLEX: the flexible-segment phase 1 (a separate instantiation, so that the
-// other modes carry none of its state).
-template <bool FLEX>
-__global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) k_persistent(SolveArgs a) {
-  __shared__ double red[kWG / kWave];
+// other modes carry none of its state).  RES: with the register-resident
+// levels; without them (a launch none of whose levels can run resident) the
+// kernel needs no rollback copy in LDS and fewer registers, and runs more
+// waves per SIMD (kStreamWaves).
+template <bool FLEX, bool RES>
+__global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(RES ? 4 : kStreamWaves)))
+k_persistent(SolveArgs a) {
+  __shared__ double red[sweep_red_doubles<false>(kSweepTiles)];
   __shared__ double s_E;
   __shared__ int s_flag;
   __shared__ int s_task;
-  __shared__ float2 roll[kWG * kMaxRPT];
+  __shared__ float2 roll[RES ? kWG * kMaxRPT : 1];
   const int xcd = blockIdx.x & 7, lb = blockIdx.x >> 3;
   Group G;
   G.g = a.g;
@@ -591,7 +599,7 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) k
       if (a.dataflow) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       d = a.tasks[t];
     }
-    if (!run_task(a, d, G, slot, part, par, red, &s_E, &s_flag, roll)) return;
+    if (!run_task<RES>(a, d, G, slot, part, par, red, &s_E, &s_flag, roll)) return;
     if constexpr (FLEX) {
       if (!group_sync(G, abort_flag, a.spin_limit, &s_flag)) return;
       if (G.member == 0 && threadIdx.x == 0) {
@@ -983,13 +991,17 @@ inline int grid_for(size_t n) {
 
 }  // namespace
 
-const void* persistent_kernel() { return (const void*)k_persistent<false>; }
+const void* persistent_kernel(bool resident) {
+  return resident ? (const void*)k_persistent<false, true> : (const void*)k_persistent<false, false>;
+}
 
 hipError_t launch_persistent(const SolveArgs& a, int grid, hipStream_t s) {
   if (a.flex)
-    hipLaunchKernelGGL(k_persistent<true>, dim3(grid), dim3(kWG), 0, s, a);
+    hipLaunchKernelGGL((k_persistent<true, true>), dim3(grid), dim3(kWG), 0, s, a);
+  else if (a.resident)
+    hipLaunchKernelGGL((k_persistent<false, true>), dim3(grid), dim3(kWG), 0, s, a);
   else
-    hipLaunchKernelGGL(k_persistent<false>, dim3(grid), dim3(kWG), 0, s, a);
+    hipLaunchKernelGGL((k_persistent<false, false>), dim3(grid), dim3(kWG), 0, s, a);
   return hipGetLastError();
 }
 

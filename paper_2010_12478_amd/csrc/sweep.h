@@ -125,12 +125,22 @@ struct Unit {
   S hx[RB], hy[RB];            // lane 0: u at column x-1, lane 63: u at column x+1
 };
 
+// LDS doubles a sweep_tiles caller provides as `red` for RT tile sums per
+// flush.
+template <bool GNORM>
+__host__ __device__ constexpr int sweep_red_doubles(int RT) {
+  return RT * (kWG / kWave) * (GNORM ? 2 : 1);
+}
+
 // Sweeps the tiles first, first + stride, ... of level L (all of them for
 // stride 1 and first 0 is not implied: pass the workgroup's own share).  For
 // every tile the energy (and with GNORM the squared gradient norm) is summed
 // in a fixed order: per lane over its rows in order, wave_sum over the
-// wavefront, then the 4 wavefronts in order; thread 0 stores it to
-// part[tile] (gpart[tile]).  Must be called by all kWG threads.
+// wavefront, then the 4 wavefronts in order (from 0.0, as block_sum); the
+// result goes to part[tile] (gpart[tile]).  The wavefront sums of up to RT
+// tiles wait in `red` (sweep_red_doubles<GNORM>(RT) doubles of LDS) and are
+// combined and stored together, so the workgroup synchronises twice per RT
+// tiles rather than twice per tile.  Must be called by all kWG threads.
 //
 // Each wavefront walks a sequence of units (a tile's rows, th/4 per
 // wavefront, in batches of kRB rows; then the next tile).  The loop is
@@ -138,9 +148,11 @@ struct Unit {
 // and halo loads of unit i + 1, and unit i is computed while those are in
 // flight, so each unit exposes one memory round trip instead of two.
 // Arithmetic is double; the stored type S is float (or double).
-template <typename S, int WRITE, bool GNORM, bool PAD, int RB = kRB>
+template <typename S, int WRITE, bool GNORM, bool PAD, int RB = kRB, int RT = 1>
 __device__ void sweep_tiles(const LevelView<S>& L, int first, int stride, int th, double* red, double* part,
                             double* gpart) {
+  static_assert(RT >= 1 && RT <= kWG, "tile sums per flush");
+  constexpr int NW = kWG / kWave;
   const int h = L.h, w = L.w;
   const int ntx = tiles_x(w);
   const int nt = tiles_of(h, w, th);
@@ -268,15 +280,34 @@ __device__ void sweep_tiles(const LevelView<S>& L, int first, int stride, int th
         }
       }
     }
-    if ((i + 1) % upt == 0) {   // last unit of this tile: order-fixed block sums
-      const double E = block_sum(lane_energy(accR, accG, lam), red);
-      if (threadIdx.x == 0) part[A.tile] = E;
+    if ((i + 1) % upt == 0) {   // last unit of this tile: its wavefront sums
+      const int k = i / upt;      // the tile's index in this workgroup's share
+      const int q = k % RT;
+      const double e = wave_sum(lane_energy(accR, accG, lam));
+      if (lane == 0) red[q * NW + wave] = e;
       accR = 0.0;
       accG = 0.0;
       if (GNORM) {
-        const double G = block_sum(accN, red);
-        if (threadIdx.x == 0) gpart[A.tile] = G;
+        const double gs = wave_sum(accN);
+        if (lane == 0) red[(RT + q) * NW + wave] = gs;
         accN = 0.0;
+      }
+      if (q == RT - 1 || k == my_tiles - 1) {   // block-uniform: combine in order and store
+        __syncthreads();
+        if ((int)threadIdx.x <= q) {
+          const int tile = first + (k - q + (int)threadIdx.x) * stride;
+          double t = 0.0;
+#pragma unroll
+          for (int w = 0; w < NW; ++w) t += red[threadIdx.x * NW + w];
+          part[tile] = t;
+          if (GNORM) {
+            double tg = 0.0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) tg += red[(RT + threadIdx.x) * NW + w];
+            gpart[tile] = tg;
+          }
+        }
+        __syncthreads();
       }
     }
     A = B;
