@@ -74,6 +74,9 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=0, help="registrations in the oracle sample")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 3 device-to-device copies of MIB MiB (calibrates the HBM byte counters)")
+    ap.add_argument("--level-probe", type=int, default=-1, metavar="L",
+                    help="only run one solver launch on pyramid level L of the headline series: 64 pairwise "
+                         "registrations, 20 fixed iterations, that level alone (per-level counter runs)")
     return ap.parse_args()
 
 
@@ -89,6 +92,37 @@ def copy_probe(mib):
         dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"copy_probe_bytes": n * 4, "copies": 3}), flush=True)
+
+
+def level_probe(level, workload):
+    """One solver launch on pyramid level `level` of the workload's series:
+    64 pairwise registrations of frames 0..64 with 20 fixed iterations on
+    that level alone (its frames restricted by the library's pyramid), the
+    library defaults otherwise.  Prints the launch's duration and its
+    pixel-updates (for counter runs split by level)."""
+    import torch
+    from dataclasses import replace
+
+    from synth import get_config, make_series
+    import paper_2010_12478_amd as rs
+
+    B, iters = 64, 20
+    cfg = get_config(workload, n_frames=B + 1)
+    S = make_series(cfg.series, device="cuda")
+    f = S.frames if level == 0 else rs.pyramid(S.frames, level + 1)[level - 1].contiguous()
+    _, H, W = f.shape
+    p = replace(cfg.solver, levels=1, max_iter=iters, fixed_iter=True)
+    rs.set_tuning(TILE_ROWS, MAX_GROUP, resident=True)
+    out = []
+    for _ in range(2):
+        rs.solve_batch(f, list(range(B)), list(range(1, B + 1)), p)
+        torch.cuda.synchronize()
+        out.append(sum(rs.last_solve_launch_ms()))
+    px = B * iters * H * W
+    print(json.dumps({"level_probe": level, "workload": cfg.name, "height": H, "width": W, "registrations": B,
+                      "iterations": iters, "pixel_updates": px, "kernel_ms": [round(x, 4) for x in out],
+                      "gpx_per_s": round(px / (out[-1] / 1000) / 1e9, 2),
+                      "algorithmic_gbs": round(SWEEP_BYTES * px / (out[-1] / 1000) / 1e9, 1)}), flush=True)
 
 
 def algorithmic_bytes(iters, n_pair, H, W, levels, max_iter):
@@ -669,6 +703,9 @@ def main():
     args = parse()
     if args.copy_probe:
         copy_probe(args.copy_probe)
+        return
+    if args.level_probe >= 0:
+        level_probe(args.level_probe, args.workload)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the scan shards across GPUs "
