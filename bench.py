@@ -75,8 +75,9 @@ def parse():
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 3 device-to-device copies of MIB MiB (calibrates the HBM byte counters)")
     ap.add_argument("--level-probe", type=int, default=-1, metavar="L",
-                    help="only run one solver launch on pyramid level L of the headline series: 64 pairwise "
-                         "registrations, 20 fixed iterations, that level alone (per-level counter runs)")
+                    help="only run one solver launch on pyramid level L of the headline series, shaped like the "
+                         "headline launch at that level: 64 pairwise registrations, 20 fixed iterations, that "
+                         "level alone (per-level counter runs)")
     return ap.parse_args()
 
 
@@ -95,11 +96,15 @@ def copy_probe(mib):
 
 
 def level_probe(level, workload):
-    """One solver launch on pyramid level `level` of the workload's series:
-    64 pairwise registrations of frames 0..64 with 20 fixed iterations on
-    that level alone (its frames restricted by the library's pyramid), the
-    library defaults otherwise.  Prints the launch's duration and its
-    pixel-updates (for counter runs split by level)."""
+    """One solver launch on pyramid level `level` of the workload's series,
+    shaped like the headline launch at that level: 64 pairwise registrations
+    of frames 0..64 with 20 fixed iterations on that level alone (its frames
+    restricted by the library's pyramid), the headline's tile height for the
+    level (the finest level's, divided by 4 per level, at least 4), every
+    level streamed (the headline's dataflow groups hold no level resident on
+    the 1024x1024 series), and the same group size (64 tasks give the group
+    the dataflow rule gives for 64 resident groups).  Prints the launch's
+    duration and its pixel-updates (for counter runs split by level)."""
     import torch
     from dataclasses import replace
 
@@ -112,15 +117,18 @@ def level_probe(level, workload):
     f = S.frames if level == 0 else rs.pyramid(S.frames, level + 1)[level - 1].contiguous()
     _, H, W = f.shape
     p = replace(cfg.solver, levels=1, max_iter=iters, fixed_iter=True)
-    rs.set_tuning(TILE_ROWS, MAX_GROUP, resident=True)
+    tile_rows = max(4, TILE_ROWS >> (2 * level))
+    rs.set_tuning(tile_rows, MAX_GROUP, resident=False)
     out = []
     for _ in range(2):
         rs.solve_batch(f, list(range(B)), list(range(1, B + 1)), p)
         torch.cuda.synchronize()
         out.append(sum(rs.last_solve_launch_ms()))
+    rs.set_tuning(TILE_ROWS, MAX_GROUP, resident=True)
     px = B * iters * H * W
     print(json.dumps({"level_probe": level, "workload": cfg.name, "height": H, "width": W, "registrations": B,
-                      "iterations": iters, "pixel_updates": px, "kernel_ms": [round(x, 4) for x in out],
+                      "iterations": iters, "tile_rows": tile_rows, "resident": False, "pixel_updates": px,
+                      "kernel_ms": [round(x, 4) for x in out],
                       "gpx_per_s": round(px / (out[-1] / 1000) / 1e9, 2),
                       "algorithmic_gbs": round(SWEEP_BYTES * px / (out[-1] / 1000) / 1e9, 1)}), flush=True)
 
@@ -181,19 +189,41 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
-def measured_traffic(workload_name):
-    """HBM bytes per solver launch from the committed rocprofv3 counter runs
-    (FETCH_SIZE and WRITE_SIZE, each scaled by what it reads for a plain
-    device copy of known size), or None once the sources have changed since
-    the counters were taken."""
+def traffic_record(workload_name):
+    """The committed counter record of the workload's solver launch, or None
+    when there is none or the kernel sources have changed since it was
+    taken."""
     try:
         with open(traffic_file(workload_name)) as f:
             t = json.load(f)
     except OSError:
         return None
-    if t.get("sources_sha256") != kernel_sources_sha256():
+    return t if t.get("sources_sha256") == kernel_sources_sha256() else None
+
+
+def measured_traffic(workload_name):
+    """HBM bytes per solver launch from rocprofv3 counter runs of that launch
+    (FETCH_SIZE and WRITE_SIZE, each scaled by what it reads for a plain
+    device copy of known size), or None."""
+    t = traffic_record(workload_name)
+    return int(t["hbm_bytes_per_dispatch"]) if t and "hbm_bytes_per_dispatch" in t else None
+
+
+def traffic_estimate(workload_name, iters, H, W, levels, max_iter, alg_bytes):
+    """HBM bytes of a launch composed from counter runs of one launch per
+    pyramid level (the level probe): the measured bytes per pixel pass of
+    each level times the launch's pixel passes on that level.  None without
+    such a record."""
+    import numpy as np
+    t = traffic_record(workload_name)
+    if not t or "bytes_per_pixel_pass" not in t:
         return None
-    return int(t["hbm_bytes_per_dispatch"])
+    bpp = t["bytes_per_pixel_pass"]
+    est = 0.0
+    for l in range(levels):
+        est += bpp[l] * int(np.minimum(iters[:, l] + 1, max_iter).sum()) * (H >> l) * (W >> l)
+    return {"bytes": int(est), "per_algorithmic": round(est / alg_bytes, 4),
+            "method": "per-level counter runs of the same instantiation (bytes per pixel pass x pixel passes)"}
 
 
 def ci95(xs):
@@ -621,7 +651,9 @@ def scan_roofline(cfg, iters, launches, steps, M):
             "launches_per_step": per_launch,
             "kernel_ms_per_launch": round(kern_ms / max(1, kern_launches), 4),
             "algorithmic_bytes_per_step": alg_step,
-            "algorithmic_bytes_per_launch": alg_step // max(1, per_launch)}
+            "algorithmic_bytes_per_launch": alg_step // max(1, per_launch),
+            "traffic_estimate": traffic_estimate(cfg.name, iters, H, W, p.levels, p.max_iter,
+                                                 alg_step) if per_launch == 1 else None}
 
 
 def level_report(iters, max_iter):
