@@ -10,7 +10,8 @@ constexpr int kWG = 256;        // threads of every tile workgroup (4 wavefronts
 constexpr int kWave = 64;
 constexpr int kTileW = 64;      // a tile row is one wavefront wide
 constexpr int kMaxLevels = 8;
-constexpr int kRB = 2;          // rows per register batch in the sweep
+constexpr int kRB = 2;          // rows per register batch in the sweep (solver instantiations with resident levels)
+constexpr int kRBStream = 4;    // the same in the streaming-only solver instantiation and the plain sweep
 constexpr int kSweepTiles = 64; // tile sums per workgroup synchronisation in the solver's sweep
 constexpr int kMaxRPT = 16;     // rows per thread of a register-resident tile at most (tile height 64)
 
@@ -128,8 +129,40 @@ struct BufView {
   __device__ __forceinline__ float f32(int v, int s) const {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, v * 4, s * 4, AUX));
   }
+  __device__ __forceinline__ double f64(int v, int s) const {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, v * 8, s * 8, AUX));
+  }
+  template <typename S>
+  __device__ __forceinline__ S load(int v, int s) const {
+    if constexpr (sizeof(S) == 4) return f32(v, s); else return f64(v, s);
+  }
+  // elements v and v + 1 (per lane) + s (wave-uniform) in one load
+  template <typename S>
+  __device__ __forceinline__ void load2(int v, int s, S& a, S& b) const {
+    if constexpr (sizeof(S) == 4) {
+      const auto p = __builtin_bit_cast(unsigned long long, __builtin_amdgcn_raw_buffer_load_b64(r, v * 4, s * 4, AUX));
+      a = __builtin_bit_cast(float, (unsigned)p);
+      b = __builtin_bit_cast(float, (unsigned)(p >> 32));
+    } else {
+      struct D2 {
+        double a, b;
+      };
+      const D2 p = __builtin_bit_cast(D2, __builtin_amdgcn_raw_buffer_load_b128(r, v * 8, s * 8, AUX));
+      a = p.a;
+      b = p.b;
+    }
+  }
   __device__ __forceinline__ void st32(int v, int s, float x) const {
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, x), r, v * 4, s * 4, 0);
+  }
+  template <typename S>
+  __device__ __forceinline__ void store(int v, int s, S x) const {
+    if constexpr (sizeof(S) == 4) {
+      st32(v, s, x);
+    } else {
+      typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+      __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, x), r, v * 8, s * 8, 0);
+    }
   }
 };
 using SharedBuf = BufView<kAuxSC1>;   // data written by other workgroups of the launch

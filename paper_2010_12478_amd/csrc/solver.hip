@@ -349,6 +349,8 @@ __device__ __forceinline__ bool run_task(const SolveArgs& a, const TaskDesc& d, 
       if (it == a.max_iter && !a.fixed_iter) status |= 1;   // REG_S_MAXITER
       continue;
     }
+    const int ths = stream_tile_rows(th);
+    const int nts = tiles_of(h, w, ths);   // <= nt: the energy slots suffice
     float* other = bufB;
     double e_prev = 0.0;
     int it = 0;
@@ -356,10 +358,11 @@ __device__ __forceinline__ bool run_task(const SolveArgs& a, const TaskDesc& d, 
       V.u = cur;
       V.out = other;
       double* pp = part + (size_t)par * a.max_tiles;
-      sweep_tiles<float, SW_UPDATE, false, true, kRB, kSweepTiles>(V, G.member, G.g, th, red, pp, nullptr);
+      sweep_tiles<float, SW_UPDATE, false, true, RES ? kRB : kRBStream, kSweepTiles>(V, G.member, G.g, ths, red, pp,
+                                                                                    nullptr);
       if (!group_sync(G, abort_flag, a.spin_limit, s_flag)) return false;
       if (threadIdx.x < kWave) {
-        const double E = wave_sum_array(pp, nt, threadIdx.x);
+        const double E = wave_sum_array(pp, nts, threadIdx.x);
         if (threadIdx.x == 0) *s_E = E;
       }
       __syncthreads();
@@ -971,7 +974,7 @@ __global__ void __launch_bounds__(kWG) k_plain_prolong(const float* uc, float* u
 
 __global__ void __launch_bounds__(kWG) k_plain_sweep(LevelView<float> V, int th, double* part) {
   __shared__ double red[kWG / kWave];
-  sweep_tiles<float, SW_UPDATE, false, true>(V, blockIdx.x, gridDim.x, th, red, part, nullptr);
+  sweep_tiles<float, SW_UPDATE, false, true, kRBStream>(V, blockIdx.x, gridDim.x, th, red, part, nullptr);
 }
 
 __global__ void __launch_bounds__(kWave) k_plain_reduce(const double* part, int n, double* E) {

@@ -56,6 +56,13 @@ __host__ __device__ inline int level_tile_rows(int th0, int l) {
   return t < 4 ? 4 : t;
 }
 
+// Tile height of a level the solver streams (not register-resident): at
+// least 16 rows, so that each wavefront's share of a tile (a quarter) holds
+// a whole batch of kRBStream rows (a shorter share loads the halo rows and
+// gathers of a full batch for fewer rows).  Every solver path streams a
+// level with these tiles, so their tile energies are summed alike.
+__host__ __device__ inline int stream_tile_rows(int th) { return th < 4 * kRBStream ? 4 * kRBStream : th; }
+
 // One pixel of the fused sweep, everything in double: bilinear sample S of T
 // from the taps i00 (x0, y0), i01 (x0 + 1, y0), i10 (x0, y0 + 1), i11 at the
 // in-cell fractions (fx, fy), with its position derivatives; residual
@@ -93,15 +100,6 @@ __device__ __forceinline__ void pixel_eval_d(double fx, double fy, double i00, d
   accG = fma(rxd, rxd, fma(dxd, dxd, fma(ryd, ryd, fma(dyd, dyd, accG))));
 }
 
-// The same from the neighbour values (c = the pixel).
-__device__ __forceinline__ void pixel_eval(double fx, double fy, double i00, double i01, double i10, double i11,
-                                           double R, double cx, double cy, double lx, double ly, double rx,
-                                           double ry, double ux, double uy, double dx, double dy, double lam,
-                                           double& accR, double& accG, double& gx, double& gy) {
-  pixel_eval_d(fx, fy, i00, i01, i10, i11, R, cx - lx, cx - rx, cx - ux, cx - dx, cy - ly, cy - ry, cy - uy,
-               cy - dy, lam, accR, accG, gx, gy);
-}
-
 // A lane's energy over its rows of a tile from its two accumulators.
 __device__ __forceinline__ double lane_energy(double accR, double accG, double lam) {
   return fma(lam, accG, accR);
@@ -116,10 +114,12 @@ __device__ __forceinline__ S gd_update(double c, double g, double tau) {
 }
 
 // Registers of one unit of work of a wavefront: rows [yb, ye) (at most RB)
-// of one tile, lane = column.
+// of one tile, lane = column.  k, x0, yb, ye and last are wave-uniform.
 template <typename S, int RB>
 struct Unit {
-  int tile, yb, ye;
+  int k;                        // the tile's index in the workgroup's share
+  int x0, yb, ye;               // first column of the tile; rows
+  bool last;                    // the tile's last unit of this wavefront
   S ax[RB + 2], ay[RB + 2];   // u at rows yb-1 .. yb+RB of this lane's column (rows clamped)
   S rr[RB];                     // R at rows yb .. yb+RB-1
   S hx[RB], hy[RB];            // lane 0: u at column x-1, lane 63: u at column x+1
@@ -143,145 +143,165 @@ __host__ __device__ constexpr int sweep_red_doubles(int RT) {
 // tiles rather than twice per tile.  Must be called by all kWG threads.
 //
 // Each wavefront walks a sequence of units (a tile's rows, th/4 per
-// wavefront, in batches of kRB rows; then the next tile).  The loop is
+// wavefront, in batches of RB rows; then the next tile).  The loop is
 // software-pipelined: the gathers of T for unit i are issued before the u, R
 // and halo loads of unit i + 1, and unit i is computed while those are in
-// flight, so each unit exposes one memory round trip instead of two.
+// flight, so each unit exposes one memory round trip instead of two; it is
+// unrolled twice so that the two units in flight swap roles instead of
+// being copied.  Every row of a unit is the same for the whole wavefront,
+// so row offsets are wave-uniform: loads and stores take them as the scalar
+// offset of a buffer instruction and the lane's column offset once per unit
+// (no per-row vector address arithmetic), and each row of u is converted to
+// double once per unit for its three uses (centre, row above, row below).
 // Arithmetic is double; the stored type S is float (or double).
 template <typename S, int WRITE, bool GNORM, bool PAD, int RB = kRB, int RT = 1>
-__device__ void sweep_tiles(const LevelView<S>& L, int first, int stride, int th, double* red, double* part,
+__device__ void sweep_tiles(const LevelView<S>& L, int first_, int stride_, int th_, double* red, double* part,
                             double* gpart) {
   static_assert(RT >= 1 && RT <= kWG, "tile sums per flush");
   constexpr int NW = kWG / kWave;
-  const int h = L.h, w = L.w;
+  // every quantity but the lane is the same across the wavefront: held in
+  // scalar registers, so everything derived from it is too
+  const int first = __builtin_amdgcn_readfirstlane(first_);
+  const int stride = __builtin_amdgcn_readfirstlane(stride_);
+  const int th = __builtin_amdgcn_readfirstlane(th_);
+  const int h = __builtin_amdgcn_readfirstlane(L.h), w = __builtin_amdgcn_readfirstlane(L.w);
+  const int pitch = __builtin_amdgcn_readfirstlane(L.pitch);
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int ntx = tiles_x(w);
   const int nt = tiles_of(h, w, th);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int rpw = th >> 2;
   const int upt = (rpw + RB - 1) / RB;            // units per tile and wavefront
   const int my_tiles = first < nt ? (nt - first + stride - 1) / stride : 0;
   const int n_units = my_tiles * upt;
-  const size_t hw = (size_t)h * w;
-  const int ihw = (int)hw;
-  const SharedBuf ub(L.u);                          // plane 0 at 0, plane 1 at hw
-  const int pitch = L.pitch;
+  const int ihw = h * w;
+  const SharedBuf ub(L.u);                          // plane 0 at 0, plane 1 at h * w
   // padded: T addressed from its (-1, -1) element, so every offset is >= 0
   const ReadBuf rb(L.R), tb(PAD ? L.T - pitch - 1 : L.T);
+  const ReadBuf ob(WRITE != SW_NONE ? (const void*)L.out : (const void*)L.R);   // stores only
   const double lam = L.lam, tau = L.tau;
 
-  auto setup = [&](int i, Unit<S, RB>& U) {
-    const int k = i / upt, b = i - k * upt;
-    U.tile = first + k * stride;
-    const int ty = U.tile / ntx;
-    const int ys = ty * th + wave * rpw;
+  // position of the next unit: tile index k in the share, its column and
+  // row in the tile grid, and the unit's batch b within the wavefront's rows
+  int nk = 0, nb = 0, nty = first / ntx, ntxc = first - nty * ntx;
+  auto setup = [&](Unit<S, RB>& U) {
+    U.k = nk;
+    U.x0 = ntxc * kTileW;
+    const int ys = nty * th + wave * rpw;
     const int yend = min(ys + rpw, h);
-    U.yb = ys + b * RB;
+    U.yb = ys + nb * RB;
     U.ye = min(U.yb + RB, yend);
+    U.last = nb == upt - 1;
+    if (++nb == upt) {   // next tile: one division per tile
+      nb = 0;
+      ++nk;
+      const int tile = first + nk * stride;
+      nty = tile / ntx;
+      ntxc = tile - nty * ntx;
+    }
   };
   auto load = [&](Unit<S, RB>& U) {
     if (U.yb >= U.ye) return;
-    const int x = (U.tile % ntx) * kTileW + lane;
-    const int xc = x < w ? x : w - 1;
+    const int x = U.x0 + lane;
+    const int xc = min(x, w - 1);
 #pragma unroll
     for (int r = 0; r < RB + 2; ++r) {
       // rows clamped to the image: at the top / bottom edge the missing
       // neighbour row is the pixel's own row
-      const int row = __mul24(clampi(U.yb - 1 + r, 0, h - 1), w);
-      U.ax[r] = ub.load<S>(row + xc);
-      U.ay[r] = ub.load<S>(ihw + row + xc);
+      const int row = clampi(U.yb - 1 + r, 0, h - 1) * w;
+      U.ax[r] = ub.template load<S>(xc, row);
+      U.ay[r] = ub.template load<S>(xc, ihw + row);
     }
 #pragma unroll
-    for (int r = 0; r < RB; ++r) U.rr[r] = rb.load<S>(__mul24(min(U.yb + r, h - 1), pitch) + xc);
+    for (int r = 0; r < RB; ++r) U.rr[r] = rb.template load<S>(xc, min(U.yb + r, h - 1) * pitch);
     if (lane == 0 || lane == kWave - 1) {
       // the column outside the tile, clamped to the image: at the image edge
       // it is the pixel's own column, so the missing difference is exactly 0
       const int xn = clampi(lane == 0 ? x - 1 : x + 1, 0, w - 1);
 #pragma unroll
       for (int r = 0; r < RB; ++r) {
-        const int row = __mul24(min(U.yb + r, h - 1), w);
-        U.hx[r] = ub.load<S>(row + xn);
-        U.hy[r] = ub.load<S>(ihw + row + xn);
+        const int row = min(U.yb + r, h - 1) * w;
+        U.hx[r] = ub.template load<S>(xn, row);
+        U.hy[r] = ub.template load<S>(xn, ihw + row);
       }
     }
   };
 
-  Unit<S, RB> A, B;
   double accR = 0.0, accG = 0.0, accN = 0.0;
-  if (n_units > 0) {
-    setup(0, A);
-    load(A);
-  }
-  for (int i = 0; i < n_units; ++i) {
-    const int x = (A.tile % ntx) * kTileW + lane;
+  // unit i in C (loaded), unit i + 1 into D
+  auto step = [&](Unit<S, RB>& C, Unit<S, RB>& D, int i) {
+    const int x = C.x0 + lane;
     const bool vx = x < w;
     const int xc = vx ? x : w - 1;
-    // gathers of T for this unit
+    // gathers of T for this unit (also for a unit with no rows, whose taps
+    // are unused: every tap address is clamped into the level, whatever u)
     S taps[RB][4];
     float flx[RB], fly[RB];  // float32 floors of the displacement (the cells)
-    if (A.yb < A.ye) {
 #pragma unroll
-      for (int r = 0; r < RB; ++r) {
-        int ix, iy;
-        flx[r] = floor_cell((float)A.ax[r + 1], ix);
-        fly[r] = floor_cell((float)A.ay[r + 1], iy);
-        const int x0 = xc + ix, y0 = min(A.yb + r, h - 1) + iy;
-        if constexpr (PAD) {
-          // the cell clamped to [-1, w-1] x [-1, h-1], offset by the border
-          const int o = __mul24(clampi(y0 + 1, 0, h), pitch) + clampi(x0 + 1, 0, w);
-          taps[r][0] = tb.load<S>(o);
-          taps[r][1] = tb.load<S>(o + 1);
-          taps[r][2] = tb.load<S>(o + pitch);
-          taps[r][3] = tb.load<S>(o + pitch + 1);
-        } else {
-          const int xa = clampi(x0, 0, w - 1), xb = clampi(x0 + 1, 0, w - 1);
-          const int ya = __mul24(clampi(y0, 0, h - 1), w), yb = __mul24(clampi(y0 + 1, 0, h - 1), w);
-          taps[r][0] = tb.load<S>(ya + xa);
-          taps[r][1] = tb.load<S>(ya + xb);
-          taps[r][2] = tb.load<S>(yb + xa);
-          taps[r][3] = tb.load<S>(yb + xb);
-        }
+    for (int r = 0; r < RB; ++r) {
+      int ix, iy;
+      flx[r] = floor_cell((float)C.ax[r + 1], ix);
+      fly[r] = floor_cell((float)C.ay[r + 1], iy);
+      const int x0 = xc + ix, y0 = min(C.yb + r, h - 1) + iy;
+      if constexpr (PAD) {
+        // the cell clamped to [-1, w-1] x [-1, h-1], offset by the border
+        const int o = __mul24(clamp0(y0 + 1, h), pitch) + clamp0(x0 + 1, w);
+        tb.template load2<S>(o, 0, taps[r][0], taps[r][1]);
+        tb.template load2<S>(o, pitch, taps[r][2], taps[r][3]);
+      } else {
+        const int xa = clamp0(x0, w - 1), xb = clamp0(x0 + 1, w - 1);
+        const int ya = __mul24(clamp0(y0, h - 1), w), yb = __mul24(clamp0(y0 + 1, h - 1), w);
+        taps[r][0] = tb.template load<S>(ya + xa, 0);
+        taps[r][1] = tb.template load<S>(ya + xb, 0);
+        taps[r][2] = tb.template load<S>(yb + xa, 0);
+        taps[r][3] = tb.template load<S>(yb + xb, 0);
       }
     }
     // loads of the next unit, in flight during this unit's arithmetic
     if (i + 1 < n_units) {
-      setup(i + 1, B);
-      load(B);
+      setup(D);
+      load(D);
     }
-    if (A.yb < A.ye) {
+    if (C.yb < C.ye) {
+      double axd[RB + 2], ayd[RB + 2];
+#pragma unroll
+      for (int r = 0; r < RB + 2; ++r) {
+        axd[r] = (double)C.ax[r];
+        ayd[r] = (double)C.ay[r];
+      }
 #pragma unroll
       for (int r = 0; r < RB; ++r) {
-        const int y = A.yb + r;
-        if (y >= A.ye) break;
-        const S cxs = A.ax[r + 1], cys = A.ay[r + 1];
+        const int y = C.yb + r;
+        if (y >= C.ye) break;
+        const S cxs = C.ax[r + 1], cys = C.ay[r + 1];
         // neighbours: lanes past the right edge hold column w - 1, so every
         // missing neighbour equals the pixel's own value (difference +0.0,
-        // the same as leaving the term out)
-        // lane 0 holds the column left of the tile in hx/hy, lane 63 the one
-        // right of it
-        const S lxs = wave_from_left(cxs, A.hx[r]), lys = wave_from_left(cys, A.hy[r]);
-        const S rxs = wave_from_right(cxs, A.hx[r]), rys = wave_from_right(cys, A.hy[r]);
-        const double cx = cxs, cy = cys;
+        // the same as leaving the term out); lane 0 holds the column left of
+        // the tile in hx/hy, lane 63 the one right of it
+        const S lxs = wave_from_left(cxs, C.hx[r]), lys = wave_from_left(cys, C.hy[r]);
+        const S rxs = wave_from_right(cxs, C.hx[r]), rys = wave_from_right(cys, C.hy[r]);
+        const double cx = axd[r + 1], cy = ayd[r + 1];
         double nR = accR, nG = accG, gx, gy;   // accumulated only for pixels inside the grid
-        pixel_eval(cx - (double)flx[r], cy - (double)fly[r], taps[r][0], taps[r][1], taps[r][2], taps[r][3],
-                   A.rr[r], cx, cy, lxs, lys,
-                   rxs, rys, A.ax[r], A.ay[r], A.ax[r + 2], A.ay[r + 2], lam, nR, nG, gx, gy);
+        pixel_eval_d(cx - (double)flx[r], cy - (double)fly[r], taps[r][0], taps[r][1], taps[r][2], taps[r][3],
+                     C.rr[r], cx - (double)lxs, cx - (double)rxs, cx - axd[r], cx - axd[r + 2],
+                     cy - (double)lys, cy - (double)rys, cy - ayd[r], cy - ayd[r + 2], lam, nR, nG, gx, gy);
         if (vx) {
           accR = nR;
           accG = nG;
-          const int o = __mul24(y, w) + x;
+          const int so = y * w;
           if (WRITE == SW_UPDATE) {
-            L.out[o] = gd_update<S>(cx, gx, tau);
-            L.out[hw + o] = gd_update<S>(cy, gy, tau);
+            ob.template store<S>(x, so, gd_update<S>(cx, gx, tau));
+            ob.template store<S>(x, ihw + so, gd_update<S>(cy, gy, tau));
           } else if (WRITE == SW_GRAD) {
-            L.out[o] = (S)gx;
-            L.out[hw + o] = (S)gy;
+            ob.template store<S>(x, so, (S)gx);
+            ob.template store<S>(x, ihw + so, (S)gy);
           }
           if (GNORM) accN += gx * gx + gy * gy;
         }
       }
     }
-    if ((i + 1) % upt == 0) {   // last unit of this tile: its wavefront sums
-      const int k = i / upt;      // the tile's index in this workgroup's share
+    if (C.last) {   // last unit of this tile: its wavefront sums
+      const int k = C.k;
       const int q = k % RT;
       const double e = wave_sum(lane_energy(accR, accG, lam));
       if (lane == 0) red[q * NW + wave] = e;
@@ -310,7 +330,16 @@ __device__ void sweep_tiles(const LevelView<S>& L, int first, int stride, int th
         __syncthreads();
       }
     }
-    A = B;
+  };
+
+  Unit<S, RB> A, B;
+  if (n_units > 0) {
+    setup(A);
+    load(A);
+  }
+  for (int i = 0; i < n_units; i += 2) {
+    step(A, B, i);
+    if (i + 1 < n_units) step(B, A, i + 1);
   }
 }
 
