@@ -99,11 +99,12 @@ def level_probe(level, workload):
     """One solver launch on pyramid level `level` of the workload's series,
     shaped like the headline launch at that level: 64 pairwise registrations
     of frames 0..64 with 20 fixed iterations on that level alone (its frames
-    restricted by the library's pyramid), the headline's tile height for the
-    level (the finest level's, divided by 4 per level, at least 4), every
-    level streamed (the headline's dataflow groups hold no level resident on
-    the 1024x1024 series), and the same group size (64 tasks give the group
-    the dataflow rule gives for 64 resident groups).  Prints the launch's
+    restricted by the library's pyramid), the headline's tile height rule for
+    the level (the finest level's, divided by 4 per level, at least 4; the
+    library streams such a level in tiles of at least 16 rows), every level
+    streamed (the headline's dataflow groups hold no level resident on the
+    1024x1024 series), and the same group size (64 tasks give the group the
+    dataflow rule gives for 64 resident groups).  Prints the launch's
     duration and its pixel-updates (for counter runs split by level)."""
     import torch
     from dataclasses import replace
@@ -127,7 +128,7 @@ def level_probe(level, workload):
     rs.set_tuning(TILE_ROWS, MAX_GROUP, resident=True)
     px = B * iters * H * W
     print(json.dumps({"level_probe": level, "workload": cfg.name, "height": H, "width": W, "registrations": B,
-                      "iterations": iters, "tile_rows": tile_rows, "resident": False, "pixel_updates": px,
+                      "iterations": iters, "level_tile_rows": tile_rows, "resident": False, "pixel_updates": px,
                       "kernel_ms": [round(x, 4) for x in out],
                       "gpx_per_s": round(px / (out[-1] / 1000) / 1e9, 2),
                       "algorithmic_gbs": round(SWEEP_BYTES * px / (out[-1] / 1000) / 1e9, 1)}), flush=True)
