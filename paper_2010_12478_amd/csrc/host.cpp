@@ -371,7 +371,7 @@ int run_plain(SolveArgs a, const std::vector<TaskDesc>& tasks, const TaskDesc* d
       float* other = bufB;
       const float* R = a.pyr[l] + (size_t)d.ref * a.fstride[l];
       const float* T = a.pyr[l] + (size_t)d.tmpl * a.fstride[l];
-      const int th = stream_tile_rows(a.thl[l]);   // the solver's tiles of a streamed level
+      const int th = stream_tile_rows(a.thl[l], h, w, kMaxGroup);   // the solver's tiles of a streamed level
       const int nt = tiles_of(h, w, th);
       double e_prev = 0.0;
       int it = 0;

@@ -349,7 +349,7 @@ __device__ __forceinline__ bool run_task(const SolveArgs& a, const TaskDesc& d, 
       if (it == a.max_iter && !a.fixed_iter) status |= 1;   // REG_S_MAXITER
       continue;
     }
-    const int ths = stream_tile_rows(th);
+    const int ths = stream_tile_rows(th, h, w, kMaxGroup);
     const int nts = tiles_of(h, w, ths);   // <= nt: the energy slots suffice
     float* other = bufB;
     double e_prev = 0.0;

@@ -56,12 +56,18 @@ __host__ __device__ inline int level_tile_rows(int th0, int l) {
   return t < 4 ? 4 : t;
 }
 
-// Tile height of a level the solver streams (not register-resident): at
-// least 16 rows, so that each wavefront's share of a tile (a quarter) holds
-// a whole batch of kRBStream rows (a shorter share loads the halo rows and
-// gathers of a full batch for fewer rows).  Every solver path streams a
-// level with these tiles, so their tile energies are summed alike.
-__host__ __device__ inline int stream_tile_rows(int th) { return th < 4 * kRBStream ? 4 * kRBStream : th; }
+// Tile height of a level the solver streams.  A level that some launch
+// could run register-resident (64-column tiles, a power-of-two height of at
+// most 64 rows that divides the level, at most max_group tiles) streams in
+// the same tiles, so that both forms sum its energy alike; any other level
+// is tiled at least 4 * kRBStream rows high, so that each wavefront's share
+// of a tile (a quarter) holds a whole batch of kRBStream rows (a shorter
+// share loads the halo rows and gathers of a full batch for fewer rows).
+__host__ __device__ inline int stream_tile_rows(int th, int h, int w, int max_group) {
+  const bool may_be_resident = w % kTileW == 0 && h % th == 0 && th <= 4 * kMaxRPT && (th & (th - 1)) == 0 &&
+                               tiles_of(h, w, th) <= max_group;
+  return may_be_resident || th >= 4 * kRBStream ? th : 4 * kRBStream;
+}
 
 // One pixel of the fused sweep, everything in double: bilinear sample S of T
 // from the taps i00 (x0, y0), i01 (x0 + 1, y0), i10 (x0, y0 + 1), i11 at the
