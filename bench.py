@@ -74,6 +74,8 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=0, help="registrations in the oracle sample")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run 3 device-to-device copies of MIB MiB (calibrates the HBM byte counters)")
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="only time the C ABI's standalone kernels on 64 x 512x512 float32 (counter runs)")
     ap.add_argument("--level-probe", type=int, default=-1, metavar="L",
                     help="only run one solver launch on pyramid level L of the headline series, shaped like the "
                          "headline launch at that level: 64 pairwise registrations, 20 fixed iterations, that "
@@ -739,6 +741,10 @@ def main():
         return
     if args.level_probe >= 0:
         level_probe(args.level_probe, args.workload)
+        return
+    if args.kernels_only:
+        import paper_2010_12478_amd as rs
+        print(json.dumps(standalone_kernels(rs)), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the scan shards across GPUs "

@@ -275,8 +275,18 @@ bool any_resident(const SolveArgs& a, int gs) {
 // Workgroups that can be resident at once for the chosen instantiation.
 int solver_slots(bool resident) { return (resident ? g.blocks_per_cu : g.blocks_per_cu_stream) * g.n_cu; }
 
+// A group of gs workgroups halved until 8 groups (one per XCD, the fewest a
+// launch has) of the instantiation it selects are resident at once: every
+// member of a group must be running for its barriers to complete, and the
+// streaming-only instantiation fits fewer workgroups per CU than the one
+// group_size counts with.
+int fit_group(const SolveArgs& a, int gs) {
+  while (gs > 1 && 8 * gs > solver_slots(any_resident(a, gs))) gs >>= 1;
+  return gs;
+}
+
 Launch plan_launch(int n_tasks, const SolveArgs& a) {
-  const int gs = group_size(n_tasks, a.H, a.W, false);
+  const int gs = fit_group(a, group_size(n_tasks, a.H, a.W, false));
   const int slots = solver_slots(any_resident(a, gs));
   int groups = std::min(slots / gs, ((n_tasks + 7) / 8) * 8);
   groups = std::max(8, (groups / 8) * 8);
@@ -313,7 +323,7 @@ int run_batched(SolveArgs a, const TaskDesc* d_tasks, int n, hipStream_t s, bool
 int run_dataflow(SolveArgs a, const TaskDesc* d_tasks, int n, int* deps, const int* deps0, int* ready,
                  const int* ready0, int n_ready0, const int* cons_off, const int* cons, hipStream_t s, bool timed) {
   if (n == 0) return REG_OK;
-  const int gs = group_size(n, a.H, a.W, true);
+  const int gs = fit_group(a, group_size(n, a.H, a.W, true));
   a.resident = any_resident(a, gs) ? 1 : 0;
   const int groups = std::max(8, (solver_slots(a.resident != 0) / gs / 8) * 8);
   const int ctrl_ints = kCtrlHead + kCtrlGroup * groups;

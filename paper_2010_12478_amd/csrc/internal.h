@@ -173,7 +173,7 @@ hipError_t launch_synth_frames(float* out, int F, int H, int W, hipStream_t s);
 // the persistent solver with (resident) or without the register-resident
 // levels; SolveArgs::resident selects the instantiation at launch
 const void* persistent_kernel(bool resident);
-constexpr int kStreamWaves = 4;   // waves per SIMD of the instantiation without resident levels
+constexpr int kStreamWaves = 3;   // waves per SIMD of the instantiation without resident levels (no spills in its sweep loop)
 hipError_t launch_persistent(const SolveArgs& a, int grid, hipStream_t s);
 hipError_t launch_reset_ctrl(int* ctrl, int n_ints, hipStream_t s);
 // *sticky |= (ctrl[1] != 0) after a persistent launch; clear: *sticky = 0

@@ -23,6 +23,8 @@
 // smooth, so a wavefront's taps fall on a few adjacent cache lines).
 #pragma once
 
+#include <type_traits>
+
 #include "device_common.h"
 
 namespace rs {
@@ -154,7 +156,11 @@ __host__ __device__ constexpr int sweep_red_doubles(int RT) {
 // and halo loads of unit i + 1, and unit i is computed while those are in
 // flight, so each unit exposes one memory round trip instead of two; it is
 // unrolled twice so that the two units in flight swap roles instead of
-// being copied.  Every row of a unit is the same for the whole wavefront,
+// being copied.  Loads and stores share one counter on this GPU, and the
+// compiler's wait for a load holds on every path into it: so every unit
+// issues the same loads (no per-lane or per-unit branch around them) and the
+// last unit is peeled off the loop, or the arithmetic's wait for its taps
+// would also drain the next unit's loads.  Every row of a unit is the same for the whole wavefront,
 // so row offsets are wave-uniform: loads and stores take them as the scalar
 // offset of a buffer instruction and the lane's column offset once per unit
 // (no per-row vector address arithmetic), and each row of u is converted to
@@ -206,10 +212,16 @@ __device__ void sweep_tiles(const LevelView<S>& L, int first_, int stride_, int 
       ntxc = tile - nty * ntx;
     }
   };
+  // The same loads for every unit and every lane (no branch), so that the
+  // compiler's count of outstanding loads is the same on every path into the
+  // arithmetic and its wait for the taps does not also drain the next unit's
+  // loads: rows clamped to the image (a unit with no rows loads the last row),
+  // and each lane loads one border column (lane 0 the one left of the tile,
+  // lane 63 the one right of it, the others their own column, unused).
   auto load = [&](Unit<S, RB>& U) {
-    if (U.yb >= U.ye) return;
     const int x = U.x0 + lane;
     const int xc = min(x, w - 1);
+    const int xn = lane == 0 ? max(x - 1, 0) : (lane == kWave - 1 ? min(x + 1, w - 1) : xc);
 #pragma unroll
     for (int r = 0; r < RB + 2; ++r) {
       // rows clamped to the image: at the top / bottom edge the missing
@@ -220,22 +232,19 @@ __device__ void sweep_tiles(const LevelView<S>& L, int first_, int stride_, int 
     }
 #pragma unroll
     for (int r = 0; r < RB; ++r) U.rr[r] = rb.template load<S>(xc, min(U.yb + r, h - 1) * pitch);
-    if (lane == 0 || lane == kWave - 1) {
-      // the column outside the tile, clamped to the image: at the image edge
-      // it is the pixel's own column, so the missing difference is exactly 0
-      const int xn = clampi(lane == 0 ? x - 1 : x + 1, 0, w - 1);
+    // the column outside the tile, clamped to the image: at the image edge
+    // it is the pixel's own column, so the missing difference is exactly 0
 #pragma unroll
-      for (int r = 0; r < RB; ++r) {
-        const int row = min(U.yb + r, h - 1) * w;
-        U.hx[r] = ub.template load<S>(xn, row);
-        U.hy[r] = ub.template load<S>(xn, ihw + row);
-      }
+    for (int r = 0; r < RB; ++r) {
+      const int row = min(U.yb + r, h - 1) * w;
+      U.hx[r] = ub.template load<S>(xn, row);
+      U.hy[r] = ub.template load<S>(xn, ihw + row);
     }
   };
 
   double accR = 0.0, accG = 0.0, accN = 0.0;
   // unit i in C (loaded), unit i + 1 into D
-  auto step = [&](Unit<S, RB>& C, Unit<S, RB>& D, int i) {
+  auto step = [&](Unit<S, RB>& C, Unit<S, RB>& D, auto next) {
     const int x = C.x0 + lane;
     const bool vx = x < w;
     const int xc = vx ? x : w - 1;
@@ -264,7 +273,7 @@ __device__ void sweep_tiles(const LevelView<S>& L, int first_, int stride_, int 
       }
     }
     // loads of the next unit, in flight during this unit's arithmetic
-    if (i + 1 < n_units) {
+    if constexpr (decltype(next)::value) {
       setup(D);
       load(D);
     }
@@ -339,13 +348,23 @@ __device__ void sweep_tiles(const LevelView<S>& L, int first_, int stride_, int 
   };
 
   Unit<S, RB> A, B;
+  using more = std::true_type;
+  using last = std::false_type;
   if (n_units > 0) {
     setup(A);
     load(A);
   }
-  for (int i = 0; i < n_units; i += 2) {
-    step(A, B, i);
-    if (i + 1 < n_units) step(B, A, i + 1);
+  // the last unit is peeled off the loop: inside it every step loads the next unit
+  int i = 0;
+  for (; i + 2 < n_units; i += 2) {
+    step(A, B, more{});
+    step(B, A, more{});
+  }
+  if (n_units - i == 2) {
+    step(A, B, more{});
+    step(B, A, last{});
+  } else if (n_units - i == 1) {
+    step(A, B, last{});
   }
 }
 
