@@ -24,6 +24,20 @@ __device__ __forceinline__ int clamp0(int v, int hi) {
   return r;
 }
 
+// XCD-aware order of a launch's blocks.  The hardware hands block L (in
+// launch order) to XCD L % 8.  In every run of 8 * chunk consecutive work
+// items, XCD x is given the chunk items [x * chunk, (x + 1) * chunk), so
+// that neighbouring items (tiles sharing halo and gather cache lines) are
+// worked on behind one L2 while the launch as a whole still sweeps the items
+// in order; the items after the last full run keep their place.  A
+// bijection of [0, total).
+__device__ __forceinline__ int xcd_item(int L, int total, int chunk) {
+  const int run = 8 * chunk;
+  if (L >= total / run * run) return L;
+  const int base = L / run * run, l = L - base;
+  return base + (l & 7) * chunk + (l >> 3);
+}
+
 // Stopping rule of a level (relative energy decrease), shared by the device
 // solver and the host loop of the plain path so both decide identically.
 __host__ __device__ inline bool level_stops(double e_prev, double e, double rel_tol) {

@@ -361,14 +361,18 @@ __global__ void __launch_bounds__(kEW) k_warp_adjoint(const S* __restrict__ g, c
   }
 }
 
-// Energy (+ gradient) of batch item blockIdx.y, tile blockIdx.x.
+// Energy (+ gradient) of one tile of one batch item (grid: tiles x items, in
+// XCD-aware order: the tiles of a row of tiles meet in one L2, which serves
+// the halo columns and gather lines they share).
 template <typename S, int WRITE, bool GNORM>
 __global__ void __launch_bounds__(kWG) k_energy_tiles(const S* __restrict__ R, const S* __restrict__ T,
                                                       const S* __restrict__ u, double lam, S* grad,
                                                       double* part, double* gpart, int H, int W, int th) {
   __shared__ double red[sweep_red_doubles<true>(1)];
   const size_t HW = (size_t)H * W;
-  const int b = blockIdx.y, nt = tiles_of(H, W, th);
+  const int nt = tiles_of(H, W, th);
+  const int item = xcd_item(blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y, tiles_x(W));
+  const int b = item / nt, tile = item - b * nt;
   LevelView<S> L;
   L.R = R + b * HW;
   L.T = T + b * HW;
@@ -382,8 +386,7 @@ __global__ void __launch_bounds__(kWG) k_energy_tiles(const S* __restrict__ R, c
   // four rows per register batch here (the u halo rows re-read per batch
   // fall from 2x to 1.5x; measured 11% faster than two), two inside the
   // persistent solver, where registers are short
-  sweep_tiles<S, WRITE, GNORM, false, 4>(L, blockIdx.x, gridDim.x, th, red, part + (size_t)b * nt,
-                                         gpart + (size_t)b * nt);
+  sweep_tiles<S, WRITE, GNORM, false, 4>(L, tile, nt, th, red, part + (size_t)b * nt, gpart + (size_t)b * nt);
 }
 
 __global__ void __launch_bounds__(kWave) k_sum_tiles(const double* part, const double* gpart, int nt,
