@@ -533,8 +533,8 @@ __device__ int flex_next(const SolveArgs& a, Group& G, FlexState& F, TaskDesc& d
 // FLEX: the flexible-segment phase 1 (a separate instantiation, so that the
 // other modes carry none of its state).  RES: with the register-resident
 // levels; without them (a launch none of whose levels can run resident) the
-// kernel needs no rollback copy in LDS and fewer registers, and runs more
-// waves per SIMD (kStreamWaves).
+// kernel needs no rollback copy in LDS and runs kStreamWaves waves per SIMD,
+// whose registers its sweep's 4-row batches take without spilling.
 template <bool FLEX, bool RES>
 __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(RES ? 4 : kStreamWaves)))
 k_persistent(SolveArgs a) {
