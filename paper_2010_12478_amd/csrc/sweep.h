@@ -160,11 +160,12 @@ __host__ __device__ constexpr int sweep_red_doubles(int RT) {
 // compiler's wait for a load holds on every path into it: so every unit
 // issues the same loads (no per-lane or per-unit branch around them) and the
 // last unit is peeled off the loop, or the arithmetic's wait for its taps
-// would also drain the next unit's loads.  Every row of a unit is the same for the whole wavefront,
-// so row offsets are wave-uniform: loads and stores take them as the scalar
-// offset of a buffer instruction and the lane's column offset once per unit
-// (no per-row vector address arithmetic), and each row of u is converted to
-// double once per unit for its three uses (centre, row above, row below).
+// would also drain the next unit's loads.  Every row of a unit is the same
+// for the whole wavefront, so row offsets are wave-uniform: loads and stores
+// take them as the scalar offset of a buffer instruction and the lane's
+// column offset once per unit (no per-row vector address arithmetic), and
+// each row of u is converted to double once per unit for its three uses
+// (centre, row above, row below).
 // Arithmetic is double; the stored type S is float (or double).
 template <typename S, int WRITE, bool GNORM, bool PAD, int RB = kRB, int RT = 1>
 __device__ void sweep_tiles(const LevelView<S>& L, int first_, int stride_, int th_, double* red, double* part,
