@@ -165,6 +165,30 @@ def test_bench_algorithmic_counts():
     assert two - one == b.SWEEP_BYTES * 16      # one more kept update of a 4x4 field
 
 
+def test_bench_traffic_records(tmp_path, monkeypatch):
+    """The roofline's traffic fields from the committed counter records: a
+    direct record gives bytes per launch, a per-level record composes bytes
+    per pixel pass with the launch's pixel passes per level, and a record
+    taken on other kernel sources gives nothing."""
+    import json
+    import numpy as np
+    b = _bench()
+    sha = b.kernel_sources_sha256()
+    monkeypatch.setattr(b, "traffic_file", lambda name: str(tmp_path / f"{name}.json"))
+    assert b.measured_traffic("none") is None and b.traffic_estimate("none", None, 1, 1, 1, 1, 1) is None
+    (tmp_path / "direct.json").write_text(json.dumps({"sources_sha256": sha, "hbm_bytes_per_dispatch": 1234}))
+    assert b.measured_traffic("direct") == 1234
+    (tmp_path / "stale.json").write_text(json.dumps({"sources_sha256": "0" * 64, "hbm_bytes_per_dispatch": 1}))
+    assert b.measured_traffic("stale") is None
+    (tmp_path / "levels.json").write_text(json.dumps({"sources_sha256": sha, "bytes_per_pixel_pass": [30.0, 20.0]}))
+    assert b.measured_traffic("levels") is None            # no direct figure for that launch
+    it = np.array([[3, 200], [0, 7]])                       # two registrations, 2 levels, cap 200
+    est = b.traffic_estimate("levels", it, 8, 8, 2, 200, 1000)
+    passes = [(4 + 1) * 64, (200 + 8) * 16]                 # t + 1 evaluations, max_iter when capped
+    assert est["bytes"] == int(30.0 * passes[0] + 20.0 * passes[1])
+    assert est["per_algorithmic"] == round(est["bytes"] / 1000, 4)
+
+
 def test_size_limits_rejected_before_any_gpu_use(rs):
     """Largest accepted frame: 16384 px per side and 2^26 pixels; beyond that,
     and for non-positive sizes or batches, every entry point fails on the host."""
