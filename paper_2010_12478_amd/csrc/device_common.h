@@ -24,6 +24,13 @@ __device__ __forceinline__ int clamp0(int v, int hi) {
   return r;
 }
 
+// clampi(v, -1, hi) as one v_med3_i32; hi is wave-uniform.
+__device__ __forceinline__ int clampm1(int v, int hi) {
+  int r;
+  asm("v_med3_i32 %0, %1, -1, %2" : "=v"(r) : "v"(v), "s"(hi));
+  return r;
+}
+
 // XCD-aware order of a launch's blocks.  The hardware hands block L (in
 // launch order) to XCD L % 8.  In every run of 8 * chunk consecutive work
 // items, XCD x is given the chunk items [x * chunk, (x + 1) * chunk), so
@@ -119,6 +126,14 @@ __device__ __forceinline__ void* uniform_ptr(const void* p) {
   const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
   const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
   return (void*)(((uint64_t)hi << 32) | lo);
+}
+
+// A double every lane of the wavefront holds, moved to scalar registers.
+__device__ __forceinline__ double uniform_f64(double x) {
+  const uint64_t v = __builtin_bit_cast(uint64_t, x);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
 // Buffer descriptor over a wave-uniform base: 32-bit element offsets keep the

@@ -1531,7 +1531,9 @@ struct RigidFlow {
 // Dataflow: the number of ready registrations varies over the run and the
 // slowest ones set its end, so g is sized for the registration instead:
 // about 32 fine-level pixels per thread and pass (at 256x256, g = 8 measured
-// 27% faster than g = 4 and 13% faster than g = 16), all slots filled.
+// as fast as g = 4 and a third faster than g = 16), all slots filled.
+constexpr int kRigidPixelsPerThread = 32;
+
 int run_rigid(RigidArgs a, const RigidTask* d_tasks, int n, const RigidFlow* f, hipStream_t s) {
   if (n == 0) return REG_OK;
   if (!g.rigid_blocks_per_cu) {
@@ -1544,21 +1546,24 @@ int run_rigid(RigidArgs a, const RigidTask* d_tasks, int n, const RigidFlow* f, 
   const int want = (n + 7) / 8 * 8;
   int gs = 1;
   if (f)
-    while (gs * 2 <= 16 && (long long)a.H * a.W >= (long long)gs * 2 * kWG * 32 && 8 * gs * 2 <= slots) gs *= 2;
+    while (gs * 2 <= kRigidMaxGroup && (long long)a.H * a.W >= (long long)gs * 2 * kWG * kRigidPixelsPerThread &&
+           8 * gs * 2 <= slots)
+      gs *= 2;
   else
-    while (gs * 2 <= 16 && (long long)want * gs * 2 <= slots) gs *= 2;
+    while (gs * 2 <= kRigidMaxGroup && (long long)want * gs * 2 <= slots) gs *= 2;
   int groups = std::max(8, slots / gs / 8 * 8);
   if (!f) groups = std::min(want, groups);
   const int ctrl_ints = kCtrlHead + kCtrlGroup * groups;
   TRY(ensure(g.rctrl, (size_t)ctrl_ints * sizeof(int)));
-  TRY(ensure(g.rpart, (size_t)groups * 2 * gs * 16 * sizeof(double)));
+  const int n_slots = groups * 3 * kRigidSlotBuf;
+  TRY(ensure(g.rpart, (size_t)n_slots * sizeof(double)));
   a.tasks = d_tasks;
   a.n_tasks = n;
   a.g = gs;
   a.ctrl = (int*)g.rctrl.p;
   a.part = (double*)g.rpart.p;
   a.spin_limit = g.spin_limit;
-  HIPCHK(launch_reset_rigid(a.ctrl, ctrl_ints, d_tasks, n, s));
+  HIPCHK(launch_reset_rigid(a.ctrl, ctrl_ints, d_tasks, n, (unsigned long long*)a.part, n_slots, s));
   if (f) {
     a.dataflow = 1;
     a.deps = f->deps;

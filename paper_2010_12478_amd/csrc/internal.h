@@ -90,6 +90,8 @@ struct RigidTask {
   int32_t* status;       // [1] or nullptr
 };
 constexpr int kRigidSums = 14;   // sum a, b, aa, bb, ab; per parameter sum g, a g, b g
+constexpr int kRigidMaxGroup = 16;   // workgroups per rigid registration
+constexpr int kRigidSlotBuf = kRigidMaxGroup * 16;   // u64 moment slots of one pass buffer: [member][16]
 struct RigidArgs {
   const float* pyr[kMaxLevelsHost];   // padded pyramid (see SolveArgs)
   size_t fstride[kMaxLevelsHost];
@@ -100,7 +102,7 @@ struct RigidArgs {
   int n_tasks;
   int g;                 // workgroups per registration
   int* ctrl;             // [0] ticket, [1] abort, per group at kCtrlHead + kCtrlGroup * id
-  double* part;          // [groups][2][g][16]: per-member partial sums, by iteration parity
+  double* part;          // [groups][3][kRigidSlotBuf]: per-member moment sums (u64 slots), by pass mod 3
   unsigned spin_limit;
   // dataflow mode (ctrl[2] / ctrl[3]: ready-queue head / tail): dependency
   // counts, the ready queue (-1: not yet filled), consumers of every task
@@ -112,7 +114,8 @@ struct RigidArgs {
 };
 const void* rigid_kernel();
 hipError_t launch_rigid(const RigidArgs& a, int grid, hipStream_t s);
-hipError_t launch_reset_rigid(int* ctrl, int n_ints, const RigidTask* tasks, int n_tasks, hipStream_t s);
+hipError_t launch_reset_rigid(int* ctrl, int n_ints, const RigidTask* tasks, int n_tasks, unsigned long long* slots,
+                              int n_slots, hipStream_t s);
 
 // Mock-operator scan (mock.hip).  A node is the frame range (i, k) as int2.
 struct MockOp {

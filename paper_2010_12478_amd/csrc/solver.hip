@@ -653,34 +653,56 @@ __device__ __forceinline__ void rigid_compose(const double* t1, const double* t2
   out[2] = s * t1[1] + c * t1[2] + t2[2];
 }
 
-// One pixel of a rigid-operator pass: the sample position phi(x) from the
-// column terms (ca dx, sa dx) and the row's dy, the bilinear value of T and
-// its derivatives there, the angle derivative grad T . dphi/dalpha, and the 14
-// moment sums.  p_x = (t1 + c_x) + G_x and p_y = (t2 + c_y) + G_y with
-// t1 = ca dx - sa dy, t2 = sa dx + ca dy, dp/dalpha = (-t2, t1): at alpha = 0
-// the positions are formed exactly as the definition reads, so integer
-// translations land on the same cells on every evaluation.  The bilinear
-// value and its derivatives share the tap differences (b0, b1: the value
-// interpolated along x on the cell's upper and lower row; dT/dy = b1 - b0);
-// multiply-adds are fused (results agree with the definition-order
+// Pixels of a rigid-operator pass.  The sample position phi(x) from the
+// column terms (ca dx, sa dx) and the row's dy: p_x = (t1 + c_x) + G_x and
+// p_y = (t2 + c_y) + G_y with t1 = ca dx - sa dy, t2 = sa dx + ca dy and
+// dp/dalpha = (-t2, t1); at alpha = 0 the positions are formed exactly as the
+// definition reads, so integer translations land on the same cells on every
+// evaluation.  A pixel is taken in two steps so that a thread can have the
+// loads of several pixels in flight: fetch (position, in-cell fraction, the
+// two tap pairs of T and the value of R) and accumulate (the bilinear value
+// and its derivatives from the shared tap differences -- b0, b1: the value
+// interpolated along x on the cell's upper and lower row, dT/dy = b1 - b0 --,
+// the angle derivative grad T . dphi/dalpha, and the 14 moment sums).
+// Multiply-adds are fused (results agree with the definition-order
 // evaluation to rounding).
-__device__ __forceinline__ void rigid_pixel(const ReadBuf& rb, const ReadBuf& tb, int pitch, int w, int h, int x,
-                                            int y, double cadx, double sadx, double ca, double sa, double cx,
-                                            double cy, double gx, double gy, double* acc) {
-  const double dy = y - cy;
-  const double t1 = cadx - sa * dy;
-  const double t2 = sadx + ca * dy;
-  const double px = (t1 + cx) + gx;
-  const double py = (t2 + cy) + gy;
+struct RigidCol {
+  double cadx, sadx, ca, sa, cx, cy, gx, gy;
+  int x, w1, h1, pitch;
+};
+struct RigidSample {
+  float i00, i01, i10, i11, av;
+  double fx, fy;
+};
+
+// Row dy = y - c_y of the column; R at element ro (per lane) + so (uniform).
+__device__ __forceinline__ void rigid_fetch(const ReadBuf& rb, const ReadBuf& tb, const RigidCol& c, double dy,
+                                            int ro, int so, RigidSample& s) {
+  const double t1 = c.cadx - c.sa * dy;
+  const double t2 = c.sadx + c.ca * dy;
+  const double px = (t1 + c.cx) + c.gx;
+  const double py = (t2 + c.cy) + c.gy;
   const double fx0 = floor(px), fy0 = floor(py);
-  const double fx = px - fx0, fy = py - fy0;
-  // the cell clamped to [-1, w-1] x [-1, h-1], offset by the border
-  const int cxi = (int)fmin(fmax(fx0, -1.0), (double)(w - 1)) + 1;
-  const int cyi = (int)fmin(fmax(fy0, -1.0), (double)(h - 1)) + 1;
-  const int o = __mul24(cyi, pitch) + cxi;
-  const double i00 = tb.f32(o, 0), i01 = tb.f32(o, 1);
-  const double i10 = tb.f32(o, pitch), i11 = tb.f32(o, pitch + 1);
-  const double av = rb.f32(__mul24(y, pitch) + x);
+  s.fx = px - fx0;
+  s.fy = py - fy0;
+  // the cell clamped to [-1, w-1] x [-1, h-1], offset by the border (the
+  // conversion saturates, so clamping the integer equals clamping the
+  // double for every finite position; a NaN position gives NaN sums either way)
+  const int cxi = clampm1((int)fx0, c.w1) + 1;
+  const int cyi = clampm1((int)fy0, c.h1) + 1;
+  const int o = __umul24((unsigned)cyi, (unsigned)c.pitch) + cxi;
+  tb.load2<float>(o, 0, s.i00, s.i01);
+  tb.load2<float>(o, c.pitch, s.i10, s.i11);
+  s.av = rb.f32(ro, so);
+}
+
+// t1 and t2 are formed again rather than kept from the fetch: the registers
+// of the batch in flight are worth more than the two multiply-adds.
+__device__ __forceinline__ void rigid_accumulate(const RigidCol& c, double dy, const RigidSample& s, double* acc) {
+  const double t1 = c.cadx - c.sa * dy;
+  const double t2 = c.sadx + c.ca * dy;
+  const double i00 = s.i00, i01 = s.i01, i10 = s.i10, i11 = s.i11, av = s.av;
+  const double fx = s.fx, fy = s.fy;
   const double d0 = i01 - i00, d1 = i11 - i10;
   const double b0 = i00 + fx * d0, b1 = i10 + fx * d1;
   const double by = b1 - b0;
@@ -703,6 +725,61 @@ __device__ __forceinline__ void rigid_pixel(const ReadBuf& rb, const ReadBuf& tb
   acc[13] += b * by;
 }
 
+// One column's rows y0, y0 + rpi, ... < y1 in row order, in batches of
+// kRigidBatch rows whose loads are issued while the previous batch is
+// accumulated (the same loads on every path into a batch's accumulation, so
+// the wait for its taps leaves the next batch's loads in flight; the last
+// batch is peeled), then the rows left over one at a time.  Within a batch
+// the rows differ by multiples of rpi: dy by exact additions, R's offset in
+// the load's scalar offset.
+constexpr int kRigidBatch = 2;   // two batches in flight fit 4 waves per SIMD without spills
+
+__device__ __forceinline__ void rigid_column(const ReadBuf& rb, const ReadBuf& tb, const RigidCol& c, int y0,
+                                             int y1, int rpi, double* acc) {
+  constexpr int P = kRigidBatch;
+  const int n = y0 < y1 ? (y1 - 1 - y0) / rpi + 1 : 0;
+  const int nb = n / P, step = P * rpi;
+  const int rstride = rpi * c.pitch;
+  RigidSample A[P], B[P];
+  auto fetch = [&](RigidSample* S, int y) {
+    const double dy = y - c.cy;
+    const int ro = __umul24((unsigned)y, (unsigned)c.pitch) + c.x;
+#pragma unroll
+    for (int j = 0; j < P; ++j) rigid_fetch(rb, tb, c, dy + (double)(j * rpi), ro, j * rstride, S[j]);
+  };
+  auto accumulate = [&](const RigidSample* S, int y) {
+    const double dy = y - c.cy;
+#pragma unroll
+    for (int j = 0; j < P; ++j) rigid_accumulate(c, dy + (double)(j * rpi), S[j], acc);
+  };
+  int y = y0;
+  if (nb > 0) {
+    fetch(A, y);
+    int b = 0;
+    for (; b + 2 < nb; b += 2, y += 2 * step) {
+      fetch(B, y + step);
+      accumulate(A, y);
+      fetch(A, y + 2 * step);
+      accumulate(B, y + step);
+    }
+    if (b + 1 < nb) {
+      fetch(B, y + step);
+      accumulate(A, y);
+      accumulate(B, y + step);
+      y += 2 * step;
+    } else {
+      accumulate(A, y);
+      y += step;
+    }
+  }
+  for (; y < y1; y += rpi) {
+    RigidSample s;
+    const double dy = y - c.cy;
+    rigid_fetch(rb, tb, c, dy, __umul24((unsigned)y, (unsigned)c.pitch) + c.x, 0, s);
+    rigid_accumulate(c, dy, s, acc);
+  }
+}
+
 // Next registration for the calling group's leader: the next ticket, or in
 // dataflow mode the next ready-queue slot once a finished registration has
 // filled it (n_tasks when none is left or the run was aborted).
@@ -723,6 +800,59 @@ __device__ int rigid_next(const RigidArgs& a, int* abort_flag) {
   }
 }
 
+// Barrier of a rigid-operator pass that also carries the moment sums: member
+// m stores its 14 sums in its slots of the pass's buffer ([member][16] u64,
+// kSlotEmpty when not yet written), and wavefront 0 polls every member's
+// slots until all are filled, then adds them in member order into s_sum.  The
+// buffers rotate over three passes as in energy_barrier: at the start of pass
+// t a member empties its slots of the buffer of pass t + 1, last filled in
+// pass t - 2 and read by every member before it published in t - 1; that
+// store lands before the member's pass-t sums do.  Called by all threads once
+// the sums are stored; returns false if the run was aborted.
+__device__ bool rigid_barrier(const Group& G, const unsigned long long* cur, int* abort_flag, unsigned spin_limit,
+                              double* s_sum, int* s_flag) {
+  if (threadIdx.x < kWave) {
+    const int lane = threadIdx.x;
+    const bool mine = lane < kRigidSums;
+    unsigned long long v[kRigidMaxGroup];
+    int ok = 1;
+    unsigned spins = 0;
+    for (;;) {
+      bool full = true;
+      if (mine) {
+#pragma unroll
+        for (int m = 0; m < kRigidMaxGroup; ++m) {   // slots of members >= g exist and stay empty
+          v[m] = __hip_atomic_load(cur + m * 16 + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          full &= (m >= G.g) | (v[m] != kSlotEmpty);
+        }
+      }
+      const int abort = ld_relaxed(abort_flag);   // in the same round trip
+      if (__all(full)) break;
+      if (abort) {
+        ok = 0;
+        break;
+      }
+      if (++spins > spin_limit) {
+        if (lane == 0) __hip_atomic_store(abort_flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    if (mine) {
+      double sum = 0.0;
+#pragma unroll
+      for (int m = 0; m < kRigidMaxGroup; ++m)
+        if (m < G.g) sum += __builtin_bit_cast(double, v[m]);
+      s_sum[lane] = sum;
+    }
+    if (lane == 0) *s_flag = ok;
+  }
+  __syncthreads();
+  if (!G.local) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return *s_flag != 0;
+}
+
 // Rigid registration with normalized cross-correlation (the paper's operator,
 // Definition "Image registration problem", Section 2.3.1): phi(x) =
 // Rot(alpha)(x - c) + c + G about the image centre c, E = 1 - NCC(R, T o phi),
@@ -736,7 +866,7 @@ __device__ int rigid_next(const RigidArgs& a, int* abort_flag) {
 // publishes them, and after the group barrier every thread adds the members'
 // sums in member order and takes the same step.  Threads own columns (a
 // thread's column terms are computed once per iteration) and walk their rows
-// two at a time, so that a lone wavefront has independent work to issue.
+// in batches (rigid_column), so that a lone wavefront keeps loads in flight.
 __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) k_rigid(RigidArgs a) {
   __shared__ double tacc[kRigidSums][kWG + 16];   // row padding: 2-way bank use on the strided reads
   __shared__ double s_sum[16];
@@ -753,8 +883,8 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) k
   G.epoch = 0;
   G.local = false;
   int* abort_flag = a.ctrl + 1;
-  double* part = a.part + (size_t)G.id * 2 * a.g * 16;
-  int tpar = 0, par = 0;
+  unsigned long long* slots = (unsigned long long*)a.part + (size_t)G.id * 3 * kRigidSlotBuf;
+  int tpar = 0, slot = 0;
   if (threadIdx.x == 0) __hip_atomic_store(&G.xcc[G.member], xcc_id(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (G.member == 0 && threadIdx.x == 0)
     __hip_atomic_store(&G.task[0], rigid_next(a, abort_flag), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -774,35 +904,42 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) k
   for (;;) {
     if (threadIdx.x == 0) s_task = ld_relaxed(&G.task[tpar]);
     __syncthreads();
-    const int t = s_task;
+    // the registration's state is the same in every thread: kept in scalar
+    // registers, so that the pixel loop has the vector registers
+    const int t = __builtin_amdgcn_readfirstlane(s_task);
     if (t >= a.n_tasks) break;
     // dataflow: the inputs were written by other groups, possibly on other
     // XCDs, and published with an agent-scope release
     if (a.dataflow) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     const RigidTask d = a.tasks[t];
+    const int ref = __builtin_amdgcn_readfirstlane(d.ref), tmpl = __builtin_amdgcn_readfirstlane(d.tmpl);
+    int32_t* const d_iters = (int32_t*)uniform_ptr(d.iters);
+    const bool leader = G.member == 0 && threadIdx.x == 0;
     double th[3] = {0.0, 0.0, 0.0};
     if (d.kind == 1) rigid_compose(d.ta, d.tb, th);
     else if (d.kind == 2) th[0] = d.ta[0], th[1] = d.ta[1], th[2] = d.ta[2];
     const double down = (double)(1 << (a.levels - 1));
-    th[1] = th[1] / down;
-    th[2] = th[2] / down;
-    int iters[kMaxLevels];
+    th[0] = uniform_f64(th[0]);
+    th[1] = uniform_f64(th[1] / down);
+    th[2] = uniform_f64(th[2] / down);
     int status = 0;
     bool dead = false;
     for (int l = a.levels - 1; l >= 0; --l) {
-      iters[l] = 0;
-      if (dead) continue;
+      if (dead) {
+        if (leader && d_iters) d_iters[l] = 0;
+        continue;
+      }
       if (l < a.levels - 1) {
         th[1] = 2.0 * th[1];
         th[2] = 2.0 * th[2];
       }
       const int h = a.H >> l, w = a.W >> l, pitch = a.pitch[l];
-      const float* Rp = a.pyr[l] + (size_t)d.ref * a.fstride[l];
-      const float* Tp = a.pyr[l] + (size_t)d.tmpl * a.fstride[l];
+      const float* Rp = a.pyr[l] + (size_t)ref * a.fstride[l];
+      const float* Tp = a.pyr[l] + (size_t)tmpl * a.fstride[l];
       const ReadBuf rb(Rp), tb(Tp - pitch - 1);   // T from its border element (-1, -1)
-      const double r2 = ((double)w * w - 1.0 + ((double)h * h - 1.0)) / 12.0;
-      const double cx = (w - 1) / 2.0, cy = (h - 1) / 2.0;
-      const double n = (double)h * w;
+      const double r2 = uniform_f64(((double)w * w - 1.0 + ((double)h * h - 1.0)) / 12.0);
+      const double cx = uniform_f64((w - 1) / 2.0), cy = uniform_f64((h - 1) / 2.0);
+      const double n = uniform_f64((double)h * w);
       const int row0 = (int)((long long)G.member * h / a.g), row1 = (int)((long long)(G.member + 1) * h / a.g);
       // thread -> (column tx + k tw, rows ty, ty + rpi, ...) of the member's band
       const int tw = w < kWG ? w : kWG, rpi = kWG / tw;
@@ -811,21 +948,35 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) k
       double e_prev = 0.0;
       int it = 0;
       for (; it < a.max_iter; ++it) {
+        // empty this member's slots of the buffer after this pass's (see rigid_barrier)
+        const int nslot = slot == 2 ? 0 : slot + 1;
+        if (G.g > 1 && threadIdx.x < kRigidSums * 16 && (threadIdx.x & 15) == 15)
+          __hip_atomic_store(slots + nslot * kRigidSlotBuf + G.member * 16 + (threadIdx.x >> 4), kSlotEmpty,
+                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         double acc[kRigidSums];
 #pragma unroll
         for (int j = 0; j < kRigidSums; ++j) acc[j] = 0.0;
         {
           double sa, ca;
           sincos(th[0], &sa, &ca);
+          sa = uniform_f64(sa);
+          ca = uniform_f64(ca);
+          RigidCol c;
+          c.ca = ca;
+          c.sa = sa;
+          c.cx = cx;
+          c.cy = cy;
+          c.gx = th[1];
+          c.gy = th[2];
+          c.w1 = w - 1;
+          c.h1 = h - 1;
+          c.pitch = pitch;
           for (int x = tx; x < w; x += tw) {
             const double dx = x - cx;
-            const double cadx = ca * dx, sadx = sa * dx;
-            int y = y_first;
-            for (; y + rpi < row1; y += 2 * rpi) {
-              rigid_pixel(rb, tb, pitch, w, h, x, y, cadx, sadx, ca, sa, cx, cy, th[1], th[2], acc);
-              rigid_pixel(rb, tb, pitch, w, h, x, y + rpi, cadx, sadx, ca, sa, cx, cy, th[1], th[2], acc);
-            }
-            if (y < row1) rigid_pixel(rb, tb, pitch, w, h, x, y, cadx, sadx, ca, sa, cx, cy, th[1], th[2], acc);
+            c.x = x;
+            c.cadx = ca * dx;
+            c.sadx = sa * dx;
+            rigid_column(rb, tb, c, y_first, row1, rpi, acc);
           }
         }
         // member partial sums through LDS: every thread's 14 sums, then the
@@ -835,7 +986,7 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) k
 #pragma unroll
         for (int j = 0; j < kRigidSums; ++j) tacc[j][threadIdx.x] = acc[j];
         __syncthreads();
-        double* pp = part + (size_t)par * a.g * 16;
+        unsigned long long* cur = slots + slot * kRigidSlotBuf;
         if (threadIdx.x < kRigidSums * 16) {   // whole 16-lane rows
           const int j = threadIdx.x >> 4, q = threadIdx.x & 15;
           double v = 0.0;
@@ -845,17 +996,24 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) k
           v += dpp_f64<0x112, 0xf, 0xf>(v);
           v += dpp_f64<0x114, 0xf, 0xe>(v);
           v += dpp_f64<0x118, 0xf, 0xc>(v);
-          if (q == 15) pp[G.member * 16 + j] = v;
+          if (q == 15) {
+            if (G.g == 1) {
+              s_sum[j] = 0.0 + v;   // the members' sum of a group of one
+            } else {
+              // the slot is this moment's arrival: the empty marker stored at
+              // the start of the pass lands first
+              if (G.local) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+              __hip_atomic_store(cur + G.member * 16 + j, __builtin_bit_cast(unsigned long long, v),
+                                 G.local ? __ATOMIC_RELAXED : __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            }
+          }
         }
-        if (!group_sync(G, abort_flag, a.spin_limit, &s_flag)) return;
-        if (threadIdx.x < kRigidSums) {
-          const SharedBuf pb(pp);
-          double v = 0.0;
-          for (int m = 0; m < a.g; ++m) v += pb.f64(m * 16 + threadIdx.x);
-          s_sum[threadIdx.x] = v;
+        if (G.g == 1) {
+          __syncthreads();
+        } else if (!rigid_barrier(G, cur, abort_flag, a.spin_limit, s_sum, &s_flag)) {
+          return;
         }
-        __syncthreads();
-        par ^= 1;
+        slot = nslot;
         double E, g0, g1, g2;
         {
 #pragma clang fp contract(off)
@@ -885,21 +1043,19 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) k
         e_prev = E;
         {
 #pragma clang fp contract(off)
-          th[0] = th[0] - a.tau * g0 / r2;
-          th[1] = th[1] - a.tau * g1;
-          th[2] = th[2] - a.tau * g2;
+          th[0] = uniform_f64(th[0] - a.tau * g0 / r2);
+          th[1] = uniform_f64(th[1] - a.tau * g1);
+          th[2] = uniform_f64(th[2] - a.tau * g2);
         }
       }
-      iters[l] = it;
+      if (leader && d_iters) d_iters[l] = it;
       if (it == a.max_iter && !a.fixed_iter) status |= 1;   // REG_S_MAXITER
     }
-    if (G.member == 0 && threadIdx.x == 0) {
+    if (leader) {
       const double nan = __builtin_nan("");
       d.out[0] = dead ? nan : th[0];
       d.out[1] = dead ? nan : th[1];
       d.out[2] = dead ? nan : th[2];
-      if (d.iters)
-        for (int l = 0; l < a.levels; ++l) d.iters[l] = iters[l];
       if (d.status) *d.status = status;
       if (a.dataflow) {
         // publish the parameters device-wide, then release the consumers whose
@@ -928,8 +1084,10 @@ __global__ void k_reset(int* ctrl, int n_ints, const TaskDesc* tasks, int n_task
     if (tasks[i].status) *tasks[i].status = 4;   // REG_S_ABORTED
 }
 
-__global__ void k_reset_rigid(int* ctrl, int n_ints, const RigidTask* tasks, int n_tasks) {
+__global__ void k_reset_rigid(int* ctrl, int n_ints, const RigidTask* tasks, int n_tasks, unsigned long long* slots,
+                              int n_slots) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_ints; i += gridDim.x * blockDim.x) ctrl[i] = 0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_slots; i += gridDim.x * blockDim.x) slots[i] = kSlotEmpty;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n_tasks; i += gridDim.x * blockDim.x)
     if (tasks[i].status) *tasks[i].status = 4;   // REG_S_ABORTED
 }
@@ -1037,9 +1195,10 @@ hipError_t launch_reset_tasks(int* ctrl, int n_ints, const TaskDesc* tasks, int 
   return hipGetLastError();
 }
 
-hipError_t launch_reset_rigid(int* ctrl, int n_ints, const RigidTask* tasks, int n_tasks, hipStream_t s) {
-  const size_t n = (size_t)(n_ints > n_tasks ? n_ints : n_tasks);
-  hipLaunchKernelGGL(k_reset_rigid, dim3(grid_for(n)), dim3(256), 0, s, ctrl, n_ints, tasks, n_tasks);
+hipError_t launch_reset_rigid(int* ctrl, int n_ints, const RigidTask* tasks, int n_tasks, unsigned long long* slots,
+                              int n_slots, hipStream_t s) {
+  const size_t n = (size_t)std::max(std::max(n_ints, n_tasks), n_slots);
+  hipLaunchKernelGGL(k_reset_rigid, dim3(grid_for(n)), dim3(256), 0, s, ctrl, n_ints, tasks, n_tasks, slots, n_slots);
   return hipGetLastError();
 }
 
