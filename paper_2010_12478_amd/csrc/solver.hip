@@ -780,6 +780,11 @@ __device__ __forceinline__ void rigid_column(const ReadBuf& rb, const ReadBuf& t
   }
 }
 
+// sin and cos of the angle, not inlined: inlined, the compiler hoists the
+// polynomials' constants out of the iteration loop and then spills them
+// (the pixel loop holds the registers), and every pass waited on their reloads.
+__device__ __attribute__((noinline)) void rigid_sincos(double a, double* s, double* c) { sincos(a, s, c); }
+
 // Next registration for the calling group's leader: the next ticket, or in
 // dataflow mode the next ready-queue slot once a finished registration has
 // filled it (n_tasks when none is left or the run was aborted).
@@ -958,7 +963,7 @@ __global__ void __launch_bounds__(kWG) __attribute__((amdgpu_waves_per_eu(4))) k
         for (int j = 0; j < kRigidSums; ++j) acc[j] = 0.0;
         {
           double sa, ca;
-          sincos(th[0], &sa, &ca);
+          rigid_sincos(th[0], &sa, &ca);
           sa = uniform_f64(sa);
           ca = uniform_f64(ca);
           RigidCol c;
