@@ -219,12 +219,23 @@ __device__ void sweep_tiles(const LevelView<S>& L, int first_, int stride_, int 
   // loads: rows clamped to the image (a unit with no rows loads the last row),
   // and each lane loads one border column (lane 0 the one left of the tile,
   // lane 63 the one right of it, the others their own column, unused).
-  auto load = [&](Unit<S, RB>& U) {
+  // P: the unit before U in this wavefront's sequence.  When U continues
+  // P's tile, its first two rows of u (the row above it and its first row)
+  // are P's last two, taken from P's registers instead of loaded again.
+  auto load = [&](Unit<S, RB>& U, const Unit<S, RB>& P) {
     const int x = U.x0 + lane;
     const int xc = min(x, w - 1);
     const int xn = lane == 0 ? max(x - 1, 0) : (lane == kWave - 1 ? min(x + 1, w - 1) : xc);
+    const bool cont = U.k == P.k;   // the same tile: U.yb = P.yb + RB
+    if (cont) {
+      U.ax[0] = P.ax[RB];
+      U.ax[1] = P.ax[RB + 1];
+      U.ay[0] = P.ay[RB];
+      U.ay[1] = P.ay[RB + 1];
+    }
 #pragma unroll
     for (int r = 0; r < RB + 2; ++r) {
+      if (r < 2 && cont) continue;
       // rows clamped to the image: at the top / bottom edge the missing
       // neighbour row is the pixel's own row
       const int row = clampi(U.yb - 1 + r, 0, h - 1) * w;
@@ -276,7 +287,7 @@ __device__ void sweep_tiles(const LevelView<S>& L, int first_, int stride_, int 
     // loads of the next unit, in flight during this unit's arithmetic
     if constexpr (decltype(next)::value) {
       setup(D);
-      load(D);
+      load(D, C);
     }
     if (C.yb < C.ye) {
       double axd[RB + 2], ayd[RB + 2];
@@ -353,7 +364,8 @@ __device__ void sweep_tiles(const LevelView<S>& L, int first_, int stride_, int 
   using last = std::false_type;
   if (n_units > 0) {
     setup(A);
-    load(A);
+    B.k = -1;   // no unit before the first
+    load(A, B);
   }
   // the last unit is peeled off the loop: inside it every step loads the next unit
   int i = 0;
