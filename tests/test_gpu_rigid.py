@@ -185,6 +185,27 @@ def test_scan_invalid_mode(rs):
         rs.scan_run_rigid(S.frames.cuda(), SolverParams(levels=1, max_iter=5, tau=RIGID_TAU), "lf", mode="plain")
 
 
+def test_repeated_runs_are_bitwise_identical(rs):
+    """The pass barrier's moment slots (emptied by every launch, rotated over
+    three passes, carried across registrations and levels) and the fixed
+    reduction order: a scan gives the same bits on every call, in both modes,
+    also after calls of other shapes and group sizes in between."""
+    announce("rigid repeated runs")
+    cfg = get_config(2, n_frames=40)
+    S = rigid_series(cfg.series)
+    frames = S.frames.cuda()
+    p = replace(cfg.solver, tau=RIGID_TAU)
+    small = SolverParams(levels=1, max_iter=20, tau=RIGID_TAU)
+    for mode in ("dataflow", "batched"):
+        first = [host(x) for x in rs.scan_run_rigid(frames, p, "hier", 4, "lf", mode=mode)]
+        rs.rigid_solve_batch(frames[:, :64, :64].contiguous(), list(range(30)), list(range(1, 31)), small)
+        rs.scan_run_rigid(frames[:5, :128, :96].contiguous(), small, "lf", mode="dataflow")
+        again = [host(x) for x in rs.scan_run_rigid(frames, p, "hier", 4, "lf", mode=mode)]
+        for a, b in zip(first, again):
+            assert np.array_equal(a.view(np.uint8), b.view(np.uint8)), mode
+        assert ((first[3] & 6) == 0).all()
+
+
 @pytest.mark.parametrize("mode", ["batched", "dataflow"])
 def test_full_size_series_sampled(rs, mode):
     """The 256-frame 256x256 series with the hierarchical plan (chunk 4,
