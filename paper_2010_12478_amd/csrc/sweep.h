@@ -158,9 +158,10 @@ __host__ __device__ constexpr int sweep_red_doubles(int RT) {
 // unrolled twice so that the two units in flight swap roles instead of
 // being copied.  Loads and stores share one counter on this GPU, and the
 // compiler's wait for a load holds on every path into it: so every unit
-// issues the same loads (no per-lane or per-unit branch around them) and the
-// last unit is peeled off the loop, or the arithmetic's wait for its taps
-// would also drain the next unit's loads.  Every row of a unit is the same
+// issues the same loads (no per-lane branch around them; a unit continuing
+// its tile only skips the two u rows it takes from the previous unit) and
+// the last unit is peeled off the loop, or the arithmetic's wait for its
+// taps would also drain the next unit's loads.  Every row of a unit is the same
 // for the whole wavefront, so row offsets are wave-uniform: loads and stores
 // take them as the scalar offset of a buffer instruction and the lane's
 // column offset once per unit (no per-row vector address arithmetic), and
@@ -213,15 +214,18 @@ __device__ void sweep_tiles(const LevelView<S>& L, int first_, int stride_, int 
       ntxc = tile - nty * ntx;
     }
   };
-  // The same loads for every unit and every lane (no branch), so that the
-  // compiler's count of outstanding loads is the same on every path into the
-  // arithmetic and its wait for the taps does not also drain the next unit's
-  // loads: rows clamped to the image (a unit with no rows loads the last row),
-  // and each lane loads one border column (lane 0 the one left of the tile,
-  // lane 63 the one right of it, the others their own column, unused).
+  // The same loads for every lane (no lane branch), so that the compiler's
+  // count of outstanding loads is the same on every path into the arithmetic
+  // and its wait for the taps does not also drain the next unit's loads:
+  // rows clamped to the image (a unit with no rows loads the last row), and
+  // each lane loads one border column (lane 0 the one left of the tile, lane
+  // 63 the one right of it, the others their own column, unused).
   // P: the unit before U in this wavefront's sequence.  When U continues
   // P's tile, its first two rows of u (the row above it and its first row)
   // are P's last two, taken from P's registers instead of loaded again.
+  // That wave-uniform branch is the one difference between paths: the wait
+  // for the taps then counts the shorter sequence, so the first unit of a
+  // tile waits for its taps four loads earlier than it needs to.
   auto load = [&](Unit<S, RB>& U, const Unit<S, RB>& P) {
     const int x = U.x0 + lane;
     const int xc = min(x, w - 1);
