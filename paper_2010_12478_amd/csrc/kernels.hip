@@ -383,9 +383,9 @@ __global__ void __launch_bounds__(kWG) k_energy_tiles(const S* __restrict__ R, c
   L.pitch = W;
   L.tau = 0.0;
   L.lam = lam;
-  // four rows per register batch here (the u halo rows re-read per batch
-  // fall from 2x to 1.5x; measured 11% faster than two), two inside the
-  // persistent solver, where registers are short
+  // four rows per register batch here (measured 11% faster than two, and
+  // faster than six or eight, which leave fewer waves per SIMD), two inside
+  // the persistent solver's instantiation with resident levels
   sweep_tiles<S, WRITE, GNORM, false, 4>(L, tile, nt, th, red, part + (size_t)b * nt, gpart + (size_t)b * nt);
 }
 
