@@ -123,8 +123,11 @@ def test_group_size_does_not_change_results(rs, max_group):
         assert torch.equal(x, y)
 
 
-@pytest.mark.parametrize("tile_rows", [4, 16, 64])
+@pytest.mark.parametrize("tile_rows", [4, 16, 24, 56, 64])
 def test_tile_rows_match_oracle(rs, tile_rows):
+    """Streamed tiles of several heights against the oracle; 24 and 56 rows
+    give each wavefront a ragged last batch after batches that pass their
+    shared rows of u on, and 56 a ragged last row of tiles."""
     announce(f"tile rows {tile_rows}")
     cfg, frames = _series(2, n_frames=3, height=96, width=80)
     p = replace(cfg.solver, levels=1, max_iter=80)
