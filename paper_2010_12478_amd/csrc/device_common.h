@@ -63,6 +63,15 @@ __device__ __forceinline__ float floor_cell(float u, int& c) {
   c = (int)fminf(fmaxf(fl, -1048576.f), 1048576.f);
   return fl;
 }
+// floor_cell of a float32 value held in double: the same floor (exact in
+// either precision) and the same cell for every finite u (the conversion
+// saturates before the clamp; a NaN u gives cell 0 here, -2^20 there, and
+// NaN arithmetic either way).
+__device__ __forceinline__ double floor_cell_d(double u, int& c) {
+  const double fl = floor(u);
+  c = min(max((int)fl, -1048576), 1048576);
+  return fl;
+}
 __device__ __forceinline__ void cell_of(float u, int& c, double& f) {
   const float fl = floor_cell(u, c);
   f = (double)u - (double)fl;

@@ -267,12 +267,19 @@ __device__ void sweep_tiles(const LevelView<S>& L, int first_, int stride_, int 
     // gathers of T for this unit (also for a unit with no rows, whose taps
     // are unused: every tap address is clamped into the level, whatever u)
     S taps[RB][4];
-    float flx[RB], fly[RB];  // float32 floors of the displacement (the cells)
+    // u in double (each row for its three uses), and the cells from its floors
+    double axd[RB + 2], ayd[RB + 2];
+#pragma unroll
+    for (int r = 0; r < RB + 2; ++r) {
+      axd[r] = (double)C.ax[r];
+      ayd[r] = (double)C.ay[r];
+    }
+    double flx[RB], fly[RB];
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
       int ix, iy;
-      flx[r] = floor_cell((float)C.ax[r + 1], ix);
-      fly[r] = floor_cell((float)C.ay[r + 1], iy);
+      flx[r] = floor_cell_d(axd[r + 1], ix);
+      fly[r] = floor_cell_d(ayd[r + 1], iy);
       const int x0 = xc + ix, y0 = min(C.yb + r, h - 1) + iy;
       if constexpr (PAD) {
         // the cell clamped to [-1, w-1] x [-1, h-1], offset by the border
@@ -294,12 +301,6 @@ __device__ void sweep_tiles(const LevelView<S>& L, int first_, int stride_, int 
       load(D, C);
     }
     if (C.yb < C.ye) {
-      double axd[RB + 2], ayd[RB + 2];
-#pragma unroll
-      for (int r = 0; r < RB + 2; ++r) {
-        axd[r] = (double)C.ax[r];
-        ayd[r] = (double)C.ay[r];
-      }
 #pragma unroll
       for (int r = 0; r < RB; ++r) {
         const int y = C.yb + r;
@@ -313,7 +314,7 @@ __device__ void sweep_tiles(const LevelView<S>& L, int first_, int stride_, int 
         const S rxs = wave_from_right(cxs, C.hx[r]), rys = wave_from_right(cys, C.hy[r]);
         const double cx = axd[r + 1], cy = ayd[r + 1];
         double nR = accR, nG = accG, gx, gy;   // accumulated only for pixels inside the grid
-        pixel_eval_d(cx - (double)flx[r], cy - (double)fly[r], taps[r][0], taps[r][1], taps[r][2], taps[r][3],
+        pixel_eval_d(cx - flx[r], cy - fly[r], taps[r][0], taps[r][1], taps[r][2], taps[r][3],
                      C.rr[r], cx - (double)lxs, cx - (double)rxs, cx - axd[r], cx - axd[r + 2],
                      cy - (double)lys, cy - (double)rys, cy - ayd[r], cy - ayd[r + 2], lam, nR, nG, gx, gy);
         if (vx) {
