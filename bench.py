@@ -659,6 +659,33 @@ def scan_roofline(cfg, iters, launches, steps, M):
                                                  alg_step) if per_launch == 1 else None}
 
 
+def stream_reference():
+    """Context for the spec peak: what a plain streaming kernel moves on this
+    GPU.  torch.add over 1 GiB float32 operands (two reads and one write per
+    element, near the solver's mix of about 2.5 read bytes per written
+    byte), mean of 10 calls timed with HIP events on the current stream after
+    one untimed call."""
+    import torch
+    n = 256 << 20
+    a = torch.rand(n, device="cuda")
+    b = torch.rand(n, device="cuda")
+    c = torch.empty(n, device="cuda")
+    torch.add(a, b, out=c)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        torch.add(a, b, out=c)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 10
+    del a, b, c
+    torch.cuda.empty_cache()
+    gbs = 12 * n / (ms / 1000.0) / 1e9
+    return {"kernel": "torch.add over 1 GiB float32 operands (read 2 : write 1)", "ms": round(ms, 4),
+            "GB/s": round(gbs, 1), "of_peak": round(gbs / PEAK_HBM_GBS, 4)}
+
+
 def level_report(iters, max_iter):
     import numpy as np
     return {"mean_iterations_per_level": [round(float(x), 2) for x in iters.mean(axis=0)],
@@ -855,6 +882,17 @@ def main():
         if not args.no_mock:
             progress("mock-operator scans")
             result["secondary"]["mock_scan"] = mock_scan_report(rs)
+    # the launch's real traffic rate against a plain streaming kernel's
+    progress("streaming reference")
+    roof = result["roofline"]
+    ref = stream_reference()
+    est = roof.get("traffic_estimate")
+    real_bytes = est["bytes"] if est else roof.get("traffic")
+    if real_bytes and roof["launches_per_step"] == 1:
+        real = real_bytes / (roof["kernel_ms_per_step"] / 1000.0) / 1e9
+        ref["solver_real_GB/s"] = round(real, 1)
+        ref["solver_real_over_stream"] = round(real / ref["GB/s"], 4)
+    roof["stream_reference"] = ref
     result["input_generation_s"] = round(gen_s, 2)
     print(json.dumps(result), flush=True)
 
