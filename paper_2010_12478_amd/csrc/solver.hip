@@ -358,8 +358,8 @@ __device__ __forceinline__ bool run_task(const SolveArgs& a, const TaskDesc& d, 
       V.u = cur;
       V.out = other;
       double* pp = part + (size_t)par * a.max_tiles;
-      sweep_tiles<float, SW_UPDATE, false, true, RES ? kRB : kRBStream, kSweepTiles>(V, G.member, G.g, ths, red, pp,
-                                                                                    nullptr);
+      sweep_tiles<float, SW_UPDATE, false, true, RES ? kRB : kRBStream, kSweepTiles, !RES>(V, G.member, G.g, ths,
+                                                                                           red, pp, nullptr);
       if (!group_sync(G, abort_flag, a.spin_limit, s_flag)) return false;
       if (threadIdx.x < kWave) {
         const double E = wave_sum_array(pp, nts, threadIdx.x);

@@ -125,9 +125,9 @@ __device__ __forceinline__ S gd_update(double c, double g, double tau) {
 // of one tile, lane = column.  k, x0, yb, ye and last are wave-uniform.
 template <typename S, int RB>
 struct Unit {
-  int k;                        // the tile's index in the workgroup's share
+  int k;                        // the tile's index in the workgroup's share (by rows of 4: the row's)
   int x0, yb, ye;               // first column of the tile; rows
-  bool last;                    // the tile's last unit of this wavefront
+  bool last;                    // the quarter's last unit
   S ax[RB + 2], ay[RB + 2];   // u at rows yb-1 .. yb+RB of this lane's column (rows clamped)
   S rr[RB];                     // R at rows yb .. yb+RB-1
   S hx[RB], hy[RB];            // lane 0: u at column x-1, lane 63: u at column x+1
@@ -140,18 +140,25 @@ __host__ __device__ constexpr int sweep_red_doubles(int RT) {
   return RT * (kWG / kWave) * (GNORM ? 2 : 1);
 }
 
-// Sweeps the tiles first, first + stride, ... of level L (all of them for
-// stride 1 and first 0 is not implied: pass the workgroup's own share).  For
-// every tile the energy (and with GNORM the squared gradient norm) is summed
-// in a fixed order: per lane over its rows in order, wave_sum over the
-// wavefront, then the 4 wavefronts in order (from 0.0, as block_sum); the
-// result goes to part[tile] (gpart[tile]).  The wavefront sums of up to RT
-// tiles wait in `red` (sweep_red_doubles<GNORM>(RT) doubles of LDS) and are
-// combined and stored together, so the workgroup synchronises twice per RT
-// tiles rather than twice per tile.  Must be called by all kWG threads.
+// Sweeps the workgroup's share of the tiles of level L: the tiles first,
+// first + stride, ... or, with ROWS4 and a level whose width in tiles is a
+// multiple of 4, the rows of 4 side-by-side tiles first, first +
+// stride, ... (in the same order as tiles, ntx / 4 such rows per row of
+// tiles).  For every tile the energy (and with GNORM the squared gradient
+// norm) is summed in a fixed order: per lane over the rows of a quarter of
+// the tile (th / 4 rows) in order, wave_sum over the wavefront, then the 4
+// quarters in order (from 0.0, as block_sum); the result goes to part[tile]
+// (gpart[tile]).  The quarter sums of up to RT tiles wait in `red`
+// (sweep_red_doubles<GNORM>(RT) doubles of LDS) and are combined and stored
+// together, so the workgroup synchronises twice per RT tiles rather than
+// twice per tile.  Must be called by all kWG threads.
 //
-// Each wavefront walks a sequence of units (a tile's rows, th/4 per
-// wavefront, in batches of RB rows; then the next tile).  The loop is
+// Each wavefront walks a sequence of units of at most RB rows: by tiles,
+// wavefront i takes quarter i of each tile of the share; by rows of 4, it
+// takes tile i of each row whole, quarter after quarter, so the 4 tiles a
+// workgroup sweeps at a time sit side by side and the border columns one
+// wavefront reads are the lines its neighbours load at the same time (the
+// same sums either way: a quarter is summed by one wavefront).  The loop is
 // software-pipelined: the gathers of T for unit i are issued before the u, R
 // and halo loads of unit i + 1, and unit i is computed while those are in
 // flight, so each unit exposes one memory round trip instead of two; it is
@@ -168,10 +175,11 @@ __host__ __device__ constexpr int sweep_red_doubles(int RT) {
 // each row of u is converted to double once per unit for its three uses
 // (centre, row above, row below).
 // Arithmetic is double; the stored type S is float (or double).
-template <typename S, int WRITE, bool GNORM, bool PAD, int RB = kRB, int RT = 1>
+template <typename S, int WRITE, bool GNORM, bool PAD, int RB = kRB, int RT = 1, bool ROWS4 = false>
 __device__ void sweep_tiles(const LevelView<S>& L, int first_, int stride_, int th_, double* red, double* part,
                             double* gpart) {
   static_assert(RT >= 1 && RT <= kWG, "tile sums per flush");
+  static_assert(!ROWS4 || RT % 4 == 0, "rows of 4 tiles are flushed whole");
   constexpr int NW = kWG / kWave;
   // every quantity but the lane is the same across the wavefront: held in
   // scalar registers, so everything derived from it is too
@@ -184,10 +192,15 @@ __device__ void sweep_tiles(const LevelView<S>& L, int first_, int stride_, int 
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int ntx = tiles_x(w);
   const int nt = tiles_of(h, w, th);
-  const int rpw = th >> 2;
-  const int upt = (rpw + RB - 1) / RB;            // units per tile and wavefront
-  const int my_tiles = first < nt ? (nt - first + stride - 1) / stride : 0;
-  const int n_units = my_tiles * upt;
+  const int rpw = th >> 2;                        // rows of a quarter of a tile
+  const int upt = (rpw + RB - 1) / RB;            // units per quarter
+  // by rows of 4 tiles: every wavefront has the same number of units, so the
+  // flushes below stay block-uniform
+  const bool rows4 = ROWS4 && ntx % 4 == 0;
+  const int nsx = ntx >> 2;
+  const int n_items = rows4 ? nt >> 2 : nt;
+  const int my_tiles = first < n_items ? (n_items - first + stride - 1) / stride : 0;   // rows4: rows of 4
+  const int n_units = my_tiles * upt * (rows4 ? 4 : 1);
   const int ihw = h * w;
   const SharedBuf ub(L.u);                          // plane 0 at 0, plane 1 at h * w
   // padded: T addressed from its (-1, -1) element, so every offset is >= 0
@@ -195,23 +208,35 @@ __device__ void sweep_tiles(const LevelView<S>& L, int first_, int stride_, int 
   const ReadBuf ob(WRITE != SW_NONE ? (const void*)L.out : (const void*)L.R);   // stores only
   const double lam = L.lam, tau = L.tau;
 
-  // position of the next unit: tile index k in the share, its column and
-  // row in the tile grid, and the unit's batch b within the wavefront's rows
-  int nk = 0, nb = 0, nty = first / ntx, ntxc = first - nty * ntx;
+  // position of the next unit: index k in the share (tile, or row of 4
+  // tiles), the tile's column and row in the tile grid, the quarter nq
+  // (rows4) and the unit's batch b within the quarter
+  int nk = 0, nq = 0, nb = 0, nty, ntxc;
+  auto place = [&](int item) {   // one division per tile (row of tiles)
+    if (rows4) {
+      nty = item / nsx;
+      ntxc = (item - nty * nsx) * 4 + wave;
+    } else {
+      nty = item / ntx;
+      ntxc = item - nty * ntx;
+    }
+  };
+  place(first);
   auto setup = [&](Unit<S, RB>& U) {
     U.k = nk;
     U.x0 = ntxc * kTileW;
-    const int ys = nty * th + wave * rpw;
+    const int ys = nty * th + (rows4 ? nq : wave) * rpw;
     const int yend = min(ys + rpw, h);
     U.yb = ys + nb * RB;
     U.ye = min(U.yb + RB, yend);
     U.last = nb == upt - 1;
-    if (++nb == upt) {   // next tile: one division per tile
+    if (++nb == upt) {
       nb = 0;
-      ++nk;
-      const int tile = first + nk * stride;
-      nty = tile / ntx;
-      ntxc = tile - nty * ntx;
+      if (!rows4 || ++nq == 4) {
+        nq = 0;
+        ++nk;
+        place(first + nk * stride);
+      }
     }
   };
   // The same loads for every lane (no lane branch), so that the compiler's
@@ -230,7 +255,7 @@ __device__ void sweep_tiles(const LevelView<S>& L, int first_, int stride_, int 
     const int x = U.x0 + lane;
     const int xc = min(x, w - 1);
     const int xn = lane == 0 ? max(x - 1, 0) : (lane == kWave - 1 ? min(x + 1, w - 1) : xc);
-    const bool cont = U.k == P.k;   // the same tile: U.yb = P.yb + RB
+    const bool cont = U.k == P.k && U.yb == P.yb + RB;   // the same tile, the next rows
     if (cont) {
       U.ax[0] = P.ax[RB];
       U.ax[1] = P.ax[RB + 1];
@@ -259,6 +284,7 @@ __device__ void sweep_tiles(const LevelView<S>& L, int first_, int stride_, int 
   };
 
   double accR = 0.0, accG = 0.0, accN = 0.0;
+  int lq = 0;   // rows4: the quarter the next last unit ends
   // unit i in C (loaded), unit i + 1 into D
   auto step = [&](Unit<S, RB>& C, Unit<S, RB>& D, auto next) {
     const int x = C.x0 + lane;
@@ -332,22 +358,36 @@ __device__ void sweep_tiles(const LevelView<S>& L, int first_, int stride_, int 
         }
       }
     }
-    if (C.last) {   // last unit of this tile: its wavefront sums
+    if (C.last) {   // last unit of a quarter of a tile: its wavefront sums
       const int k = C.k;
-      const int q = k % RT;
+      const int cq = rows4 ? lq : wave;   // the quarter this unit ends
+      lq = (lq + 1) & 3;
+      const int slot = (rows4 ? 4 * k + wave : k) % RT;   // the tile's place in the flush
       const double e = wave_sum(lane_energy(accR, accG, lam));
-      if (lane == 0) red[q * NW + wave] = e;
+      if (lane == 0) red[slot * NW + cq] = e;
       accR = 0.0;
       accG = 0.0;
       if (GNORM) {
         const double gs = wave_sum(accN);
-        if (lane == 0) red[(RT + q) * NW + wave] = gs;
+        if (lane == 0) red[(RT + slot) * NW + cq] = gs;
         accN = 0.0;
       }
-      if (q == RT - 1 || k == my_tiles - 1) {   // block-uniform: combine in order and store
+      // items (tiles, or rows of 4 tiles) per flush; the same unit of every
+      // wavefront, so block-uniform
+      const int per = rows4 ? RT / 4 : RT;
+      const int q = k % per;
+      if ((!rows4 || cq == NW - 1) && (q == per - 1 || k == my_tiles - 1)) {   // combine in order and store
         __syncthreads();
-        if ((int)threadIdx.x <= q) {
-          const int tile = first + (k - q + (int)threadIdx.x) * stride;
+        if ((int)threadIdx.x < (rows4 ? 4 * (q + 1) : q + 1)) {
+          const int i = (k - q) * (rows4 ? 4 : 1) + (int)threadIdx.x;   // tile index in the share
+          int tile;
+          if (rows4) {
+            const int item = first + (i >> 2) * stride;
+            const int ty = item / nsx;
+            tile = ty * ntx + (item - ty * nsx) * 4 + (i & 3);
+          } else {
+            tile = first + i * stride;
+          }
           double t = 0.0;
 #pragma unroll
           for (int w = 0; w < NW; ++w) t += red[threadIdx.x * NW + w];
