@@ -160,6 +160,47 @@ def test_resident_levels_match_streaming_bitwise(rs, tile_rows, H, W, levels):
             assert host(b[1])[k].tolist() == list(w.iters)
 
 
+@pytest.mark.parametrize("H,W,levels,tile_rows,group",
+                         [(128, 256, 2, 64, 128), (256, 512, 1, 16, 1), (64, 256, 1, 4, 1)])
+def test_rows_of_four_tiles_match_resident_bitwise(rs, H, W, levels, tile_rows, group):
+    """A streamed level whose width in tiles is a multiple of 4 is swept with
+    every wavefront on a whole tile, the four of a workgroup side by side;
+    its energies add the same quarter sums in the same order as the
+    register-resident form, so the bits agree.  With one workgroup per
+    registration the 256x512 level is 32 rows of four tiles (two flushes of
+    the tile sums); 4-row tiles make every quarter one row."""
+    announce(f"rows of four vs resident {H}x{W} L={levels} th={tile_rows} g={group}")
+    cfg, frames = _series(2, n_frames=3, height=H, width=W)
+    p = replace(cfg.solver, levels=levels, max_iter=60)
+    ref, tmpl = [0, 1], [1, 2]
+    rs.set_tuning(tile_rows, group, resident=False)
+    a = rs.solve_batch(frames.cuda(), ref, tmpl, p)
+    rs.set_tuning(tile_rows, 128, resident=True)
+    b = rs.solve_batch(frames.cuda(), ref, tmpl, p)
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+    want = _oracle_batch(frames, ref, tmpl, p)
+    for k, w in enumerate(want):
+        assert np.abs(host(a[0])[k] - w.u).max() <= TOL_PX
+        assert host(a[1])[k].tolist() == list(w.iters)
+
+
+@pytest.mark.parametrize("H,W", [(100, 200), (70, 260)])
+def test_rows_of_four_tiles_ragged_match_oracle(rs, H, W):
+    """Streamed levels with a last column and a last row of tiles partly
+    outside the image: 200 columns are 4 tiles (swept as a row of four), 260
+    are 5 (swept by quarters)."""
+    announce(f"rows of four ragged {H}x{W}")
+    cfg, frames = _series(2, n_frames=3, height=H, width=W)
+    p = replace(cfg.solver, levels=1, max_iter=60)
+    rs.set_tuning(16, 2, resident=False)
+    u, iters, _ = rs.solve_batch(frames.cuda(), [0, 1], [1, 2], p)
+    want = _oracle_batch(frames, [0, 1], [1, 2], p)
+    for b, w in enumerate(want):
+        assert np.abs(host(u)[b] - w.u).max() <= TOL_PX
+        assert host(iters)[b].tolist() == list(w.iters)
+
+
 def test_resident_stop_keeps_previous_state_and_nonfinite(rs):
     """A level that stops on the energy test returns the state its last
     iteration started from (the LDS copy); a non-finite frame still flags the
